@@ -1,0 +1,245 @@
+"""Oracle pins on the nonlinear (and layered) walls (CPU only).
+
+  * the discrete balance identity, exact for any coefficient law: it holds
+    because each face coefficient is shared by its two nodes, so it checks the
+    stencil, the Robin half cells, the layer interfaces and the c_TM / k_TM
+    cross terms without restating the update;
+  * the defining equation of the scheme (eq. DF_NL with u_j^n replaced by the
+    average of levels n+1 and n-1, Sec. 3.1) as a per-node residual;
+  * conservation of the moisture content of an isothermal, sealed wall to
+    O(dt^2);
+  * convergence towards a fine-grid Crank-Nicolson solution (the paper's
+    Chebfun reference is not available) and the O(dt^2) error of Sec. 4;
+  * the compensated flux integrals against an exactly rounded sum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import trapezoid_weights
+from paper_1703_10119_amd import workloads as wl
+
+
+def _layered_wall():
+    w = wl.layered_batch(1, seed=11, nx_lo=60, nx_hi=60)
+    w["n_layers"][:] = 3
+    F = wl.LAYER_FIELDS
+    for l, (th, s) in enumerate(((0.03, 0.5), (0.05, 3.0), (0.04, 1.0))):
+        w["layer"][0, l, F.index("thick")] = th
+        w["layer"][0, l, F.index("k0")] *= s
+        w["layer"][0, l, F.index("kM0")] /= s
+        w["layer"][0, l, F.index("c0")] *= 1 + 0.3 * l
+    w["qinf"][0] = (35.0, -12.0)
+    w["ginf"][0] = (3e-6, 0.0)
+    return w
+
+
+def _balance_residuals(sim, w_index, wall, dt, Lv):
+    """Residual of the moisture and heat balance identities for one step."""
+    nx = int(wall["nx"][w_index])
+    L = float(wall["layer"][w_index, :int(wall["n_layers"][w_index]),
+                            wl.LAYER_FIELDS.index("thick")].sum())
+    dx = L / (nx - 1)
+    r, s = dt / dx ** 2, dt / dx
+    node, face = sim.coeffs(w_index)
+    Tm, Pm = sim.fields(w_index, 1)
+    Tc, Pc = sim.fields(w_index, 0)
+    sim.step(1)
+    Tn, Pn = sim.fields(w_index, 0)
+    now, _ = sim.fluxes()
+    om = trapezoid_weights(nx)
+    K = np.zeros((nx, 3))
+    K[1:] += face
+    K[:-1] += face
+    K[0] = 2 * face[0]
+    K[-1] = 2 * face[-1]
+    cTT, cM, cTM = node.T
+    KT, KM, KX = K.T
+    m_terms = om * ((cM + r * KM) * Pn - 2 * r * KM * Pc - (cM - r * KM) * Pm)
+    m_rhs = 2 * s * (now[w_index, 0, 1] + now[w_index, 1, 1])
+    h_terms = om * ((cTT + r * KT) * Tn - 2 * r * KT * Tc - (cTT - r * KT) * Tm
+                    + (cTM + r * KX) * Pn - 2 * r * KX * Pc - (cTM - r * KX) * Pm)
+    h_rhs = 2 * s * (now[w_index, 0, 0] + now[w_index, 1, 0])
+    m_scale = np.sum(np.abs(om * (cM + r * KM) * Pn)) + abs(m_rhs)
+    h_scale = np.sum(np.abs(om * (cTT + r * KT) * Tn)) + np.sum(np.abs(om * (cTM + r * KX) * Pn))
+    return (m_terms.sum() - m_rhs) / m_scale, (h_terms.sum() - h_rhs) / h_scale
+
+
+@pytest.mark.parametrize("case", ["single", "layered"])
+def test_balance_identity_every_step(case):
+    w = wl.single_wall() if case == "single" else _layered_wall()
+    dt = 1.0 if case == "single" else 20.0
+    cfg = wl.default_config(dt=dt)
+    sim = oracle.RefSim(w, cfg)
+    sim.step(1)            # start-up step (forward-Euler sub-steps)
+    sim.step(500)          # let the surface forcing develop
+    if case == "layered":
+        lay = sim.layers(0)
+        assert set(lay.tolist()) == {0, 1, 2}
+    for _ in range(20):
+        rm, rh = _balance_residuals(sim, 0, w, dt, cfg["Lv"])
+        assert abs(rm) < 1e-13 and abs(rh) < 1e-13, (rm, rh)
+
+
+def test_defining_equation_residual_per_node():
+    """Each node satisfies the DF form of its own half-cell / cell balance."""
+    w = _layered_wall()
+    dt = 30.0
+    cfg = wl.default_config(dt=dt)
+    sim = oracle.RefSim(w, cfg)
+    sim.step(200)
+    nx = int(w["nx"][0])
+    L = float(w["layer"][0, :3, 0].sum())
+    dx = L / (nx - 1)
+    node, face = sim.coeffs(0)
+    Tm, Pm = sim.fields(0, 1)
+    Tc, Pc = sim.fields(0, 0)
+    sim.step(1)
+    Tn, Pn = sim.fields(0, 0)
+    now, _ = sim.fluxes()
+    Tb, Pb = 0.5 * (Tn + Tm), 0.5 * (Pn + Pm)       # DF replacement of u_j^n
+    cTT, cM, cTM = node.T
+    kT, kM, kX = face.T
+    for j in range(nx):
+        width = dx if 0 < j < nx - 1 else dx / 2
+        flux_m = flux_h = 0.0
+        if j > 0:
+            flux_m += kM[j - 1] * (Pc[j - 1] - Pb[j]) / dx
+            flux_h += kT[j - 1] * (Tc[j - 1] - Tb[j]) / dx + kX[j - 1] * (Pc[j - 1] - Pb[j]) / dx
+        if j < nx - 1:
+            flux_m += kM[j] * (Pc[j + 1] - Pb[j]) / dx
+            flux_h += kT[j] * (Tc[j + 1] - Tb[j]) / dx + kX[j] * (Pc[j + 1] - Pb[j]) / dx
+        if j in (0, nx - 1):
+            side = 0 if j == 0 else 1
+            flux_m += now[0, side, 1]
+            flux_h += now[0, side, 0]
+        res_m = width * cM[j] * (Pn[j] - Pm[j]) / (2 * dt) - flux_m
+        res_h = width * (cTT[j] * (Tn[j] - Tm[j]) + cTM[j] * (Pn[j] - Pm[j])) / (2 * dt) - flux_h
+        sm = width * cM[j] * abs(Pn[j]) / dt + abs(flux_m)
+        sh = width * cTT[j] * abs(Tn[j]) / dt
+        assert abs(res_m) < 1e-12 * sm and abs(res_h) < 1e-12 * sh, (j, res_m, res_h)
+
+
+def test_isothermal_moisture_content_drift_is_second_order():
+    """Sealed isothermal wall (no cross terms): the PDE conserves the moisture
+    content int cM0 (P + aC P^2 / (2 Ps)) dx; DF's drift shrinks ~dt^2."""
+    nx = 41
+    w = wl.single_wall(nx=nx)
+    F = wl.LAYER_FIELDS
+    w["layer"][0, 0, F.index("bTM")] = 0.0
+    w["layer"][0, 0, F.index("fTM")] = 0.0
+    w["hT"][0] = (0.0, 0.0)
+    w["hM"][0] = (0.0, 0.0)
+    dx = 0.1 / (nx - 1)
+    x = np.arange(nx) * dx
+    Ps = oracle.psat(293.0)
+    P0 = Ps * (0.5 + 0.3 * np.cos(math.pi * x / 0.1))
+    om = trapezoid_weights(nx)
+    cM0 = w["layer"][0, 0, F.index("cM0")]
+    aC = w["layer"][0, 0, F.index("aC")]
+
+    def content(P):
+        return np.sum(om * cM0 * (P + aC * P * P / (2 * Ps))) * dx
+
+    drifts = []
+    t_end = 6 * 3600.0
+    for dt in (200.0, 100.0, 50.0, 25.0):
+        sim = oracle.RefSim(w, wl.default_config(dt=dt))
+        sim.set_fields(0, 0, np.full(nx, 293.0), P0)
+        sim.step(1)                    # forward-Euler start-up
+        c1 = content(sim.fields(0)[1])
+        sim.step(int(t_end / dt) - 1)
+        drifts.append(abs(content(sim.fields(0)[1]) - c1) / c1)
+    orders = [math.log2(drifts[i] / drifts[i + 1]) for i in range(3)]
+    assert drifts[-1] < 2e-5
+    assert all(1.8 < o < 2.5 for o in orders[1:]), (orders, drifts)
+
+
+def _fine_reference(w, t_end, nx_fine, dt_fine):
+    wf = {k: np.array(v, copy=True) for k, v in w.items()}
+    wf["nx"][:] = nx_fine
+    T, P, it = oracle.implicit_run(wf, 0, dt_fine, wl.LV, int(round(t_end / dt_fine)),
+                                   theta=0.5, eta=1e-12)
+    return T, P, it
+
+
+def test_converges_to_fine_crank_nicolson_at_second_order_in_dt():
+    """Nonlinear single wall, 2 h of forcing: the DF error against a 4x finer
+    Crank-Nicolson grid falls as dt^2 while the time error dominates, and is
+    below 3e-4 of the field range at dt = 2 s (cf. the ~1e-4 dimensionless
+    errors reported in Sec. 4)."""
+    w = wl.single_wall(nx=101)
+    # start off equilibrium so that both fields move from the first step
+    w["T0"][:] = 288.0
+    w["RH0"][:] = 0.7
+    t_end = 7200.0
+    Tf, Pf, it = _fine_reference(w, t_end, 401, 0.125)
+    assert 1.0 <= it < 10.0
+    Tf, Pf = Tf[::4], Pf[::4]
+    errs = {}
+    for dt in (2.0, 8.0, 16.0, 32.0, 64.0):
+        sim = oracle.RefSim(w, wl.default_config(dt=dt))
+        sim.step(int(t_end / dt))
+        T, P = sim.fields(0)
+        errs[dt] = max(np.max(np.abs(T - Tf)) / np.ptp(Tf), np.max(np.abs(P - Pf)) / np.ptp(Pf))
+    # middle region: O(dt^2); small dt: the spatial error floor; large dt: the
+    # error grows faster than dt^2 (the three regions described in Sec. 4)
+    o1 = math.log2(errs[16.0] / errs[8.0])
+    o2 = math.log2(errs[32.0] / errs[16.0])
+    assert 1.6 < o1 < 2.4 and 1.6 < o2 < 2.4, errs
+    assert errs[2.0] < 3e-4, errs
+    assert errs[64.0] / errs[32.0] > 4.0, errs
+
+
+def test_euler_implicit_is_first_order_and_needs_subiterations():
+    """Comparator of Sec. 5.2: Euler implicit with fixed-point sub-iterations
+    is first order in dt and takes more than one iteration per step."""
+    w = wl.single_wall(nx=51)
+    w["T0"][:] = 288.0
+    w["RH0"][:] = 0.7
+    t_end = 3600.0
+    Tf, Pf, _ = _fine_reference(w, t_end, 51, 0.25)
+    e = []
+    for dt in (60.0, 30.0):
+        T, P, it = oracle.implicit_run(w, 0, dt, wl.LV, int(t_end / dt), theta=1.0, eta=1e-10)
+        assert it > 1.5
+        e.append(np.max(np.abs(P - Pf)) / np.ptp(Pf))
+    assert 0.8 < math.log2(e[0] / e[1]) < 1.2, e
+
+
+def test_flux_integrals_match_exactly_rounded_sum():
+    """Neumaier-compensated integrals equal math.fsum of dt * applied flux."""
+    w = wl.uniform_batch(3, seed=5, nx=41)
+    dt = 7.0
+    sim = oracle.RefSim(w, wl.default_config(dt=dt, startup=1))
+    parts = [[[[] for _ in range(2)] for _ in range(2)] for _ in range(3)]
+    for _ in range(3000):
+        sim.step(1)
+        now, _ = sim.fluxes()
+        for i in range(3):
+            for s in range(2):
+                for f in range(2):
+                    parts[i][s][f].append(dt * now[i, s, f])
+    _, integ = sim.fluxes()
+    for i in range(3):
+        for s in range(2):
+            for f in range(2):
+                exact = math.fsum(parts[i][s][f])
+                assert integ[i, s, f] == pytest.approx(exact, rel=1e-15, abs=1e-300)
+
+
+def test_forward_euler_startup_matches_fine_solution():
+    """The start-up step (forward-Euler sub-steps of dt/m, m from the
+    explicit stability bound) lands on the fine-grid solution at t = dt."""
+    w = wl.uniform_batch(1, seed=9, nx=101)
+    dt = 60.0
+    sim = oracle.RefSim(w, wl.default_config(dt=dt))
+    m = sim.startup_substeps(0)
+    assert m > 1
+    sim.step(1)
+    T, P = sim.fields(0)
+    Tf, Pf, _ = oracle.implicit_run(w, 0, dt / 64, wl.LV, 64, theta=0.5, eta=1e-13)
+    assert np.max(np.abs(T - Tf)) < 5e-3 * max(np.ptp(Tf), 1e-3) + 1e-6
+    assert np.max(np.abs(P - Pf)) < 5e-3 * max(np.ptp(Pf), 1e-3) + 1e-6
