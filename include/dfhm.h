@@ -1,0 +1,209 @@
+/*
+ * dfhm.h -- C ABI of the MI355X Dufort-Frankel hygrothermal wall / room solver.
+ *
+ * The library advances batches of 1-D porous walls under the coupled heat and
+ * vapour-pressure balance of Gasparin, Berger, Dutykh & Mendes (arXiv
+ * 1703.10119), Sec. 2 eq. (2.2), with Robin surface exchange eq. (2.3),
+ * uniform initial state eq. (2.4), the nonlinear Dufort-Frankel update of
+ * Sec. 3.1 (eqs. DF_NL, DF_NL_RHS) applied to the weakly coupled pair as in
+ * App. A (moisture first, then heat with the new vapour pressure, eq.
+ * DF_eq2b), the DF-averaged surface value in the Robin term (eq. bc_v), and
+ * optionally a lumped room-air balance per zone (Sec. 5.1, eq. LAV_equation
+ * with the exchange terms of eq. LAV_couplage) coupled explicitly as in
+ * Sec. 5.3 (eq. wbse_tn_exp).  All time stepping runs in HIP kernels on one
+ * gfx950 device.
+ *
+ * Conventions
+ *   - Units are SI: K, Pa, m, s, W, kg.
+ *   - Side 0 of a wall is x = 0, side 1 is x = L.  Surface fluxes are
+ *     positive INTO the wall on both sides: heat in W/m2, vapour in kg/(m2 s).
+ *   - Every call returns a dfhm_status; nothing aborts across the ABI.  On an
+ *     error the context is unchanged, the message is kept for
+ *     dfhm_last_error(), and a non-finite state latches DFHM_E_STATE until
+ *     fields are set again.
+ *   - Host descriptors are copied at the call; the caller may free them
+ *     afterwards.  Host output buffers are caller-owned.
+ *   - One context must not be used by two threads at once.  Contexts are
+ *     independent of each other.
+ *   - Work is queued on the stream given in dfhm_config (NULL = the default
+ *     stream).  Calls that return host data synchronise that stream.
+ */
+#ifndef DFHM_H
+#define DFHM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dfhm_ctx dfhm_ctx;
+
+typedef enum {
+    DFHM_OK = 0,
+    DFHM_E_INVAL = 1,     /* bad argument or descriptor */
+    DFHM_E_NOMEM = 2,     /* device allocation failed or arena too small */
+    DFHM_E_DEVICE = 3,    /* a HIP call failed */
+    DFHM_E_NONFINITE = 4, /* a step produced a non-finite value */
+    DFHM_E_STATE = 5,     /* call not allowed in the current state */
+    DFHM_E_UNSTABLE = 6   /* explicit room step would be unstable at dt */
+} dfhm_status;
+
+enum { DFHM_FP64 = 0, DFHM_FP32 = 1 };
+/* Start of the three-level scheme (the paper leaves it open):
+ *   FTCS   -- the first step is m forward-Euler sub-steps of dt/m, with m =
+ *             ceil(2 dt / b), b the explicit stability bound of the wall at
+ *             its initial state (dimensional form of eqs. cfl_heat_Eq and
+ *             cfl_moisture_Eq, surface exchange included);
+ *   REPEAT -- level n-1 := level 0 and the first step is a DF step. */
+enum { DFHM_START_FTCS = 0, DFHM_START_REPEAT = 1 };
+/* Kernel schedule: STREAM = one launch per step over HBM-resident levels;
+ * RESIDENT = one persistent launch per chunk of steps, each workgroup keeping
+ * its walls' levels on chip; AUTO = chosen by the autotuner. */
+enum { DFHM_SCHED_AUTO = 0, DFHM_SCHED_STREAM = 1, DFHM_SCHED_RESIDENT = 2 };
+
+/* x(t) = mean + amp * sin(2 pi t / period_s + phase) */
+typedef struct { double mean, amp, period_s, phase; } dfhm_sine;
+
+/* One material layer.  With phi = Pv / Ps(T), theta = T - 273.15 and
+ * Ps(T) = 610.94 exp(17.625 theta / (theta + 243.04)) Pa (Magnus form):
+ *   k_TT = k0  (1 + a_T phi)        W/(m K)
+ *   k_M  = kM0 (1 + a_M phi^2)      s
+ *   k_TM = b_TM k_M                 m2/s      (k_TM = Lv delta_v, Sec. 2)
+ *   c_TT = c0  (1 + c_T phi)        J/(m3 K)
+ *   c_M  = cM0 (1 + c_M phi)        s2/m2
+ *   c_TM = (e_TM + f_TM theta) c_M  (c_TM = c_w T f'/Ps, Sec. 2)
+ * All-zero shape coefficients (a_T, a_M, c_T, c_M, f_TM) give the
+ * constant-coefficient walls of Sec. 6.1 (Table 2). */
+typedef struct {
+    double thickness_m;
+    double k0, a_T, kM0, a_M, b_TM, c0, c_T, cM0, c_M, e_TM, f_TM;
+} dfhm_layer;
+
+/* One wall: nx uniform nodes over L = sum of layer thicknesses (dx =
+ * L/(nx-1); both surfaces are nodes).  Node j belongs to the first layer
+ * whose right end is >= j dx; a face between nodes of different layers takes
+ * the harmonic mean of the two layers' conductivities at the face state
+ * (zero when both are zero).  T_amb / RH_amb give the outdoor air of each
+ * side (ignored on a side coupled to a room).  T0 / RH0 give the uniform
+ * initial state (Pv0 = RH0 Ps(T0)).  area_m2 is used by the room balance. */
+typedef struct {
+    int32_t nx, n_layers;           /* 3 <= nx <= 2048, 1 <= n_layers <= 3 */
+    dfhm_layer layer[3];
+    double h_T[2], h_M[2];          /* W/(m2 K), s/m;  >= 0 */
+    double q_inf[2], g_inf[2];      /* extra heat / liquid flux into the wall */
+    dfhm_sine T_amb[2], RH_amb[2];
+    double T0, RH0, area_m2;
+} dfhm_wall;
+
+/* One perfectly mixed zone (Sec. 5.1): w ~ Pv / Pv_ref, ventilation flow
+ * g_v = ach * rho_a V / 3600 kg/s from outdoor air (T_out, RH_out), moisture
+ * source g_o (latent heat Lv g_o to the air) and heat source Q_h, both
+ * piecewise constant over n_sched slots of sched_dt_s, repeated
+ * periodically. */
+typedef struct {
+    double volume_m3, ach_per_h, T0, RH0;
+    dfhm_sine T_out, RH_out;
+    int32_t n_sched;                /* >= 1 */
+    double sched_dt_s;              /* > 0 */
+    const double *g_o_kg_s;         /* [n_sched] host */
+    const double *Q_h_W;            /* [n_sched] host */
+} dfhm_room;
+
+typedef struct {
+    int32_t precision;      /* DFHM_FP64 | DFHM_FP32 (FP32 fields stored as
+                               deviations from each wall's initial state; the
+                               outdoor phase, flux integrals and room air stay
+                               FP64) */
+    int32_t startup;        /* DFHM_START_* */
+    int32_t schedule;       /* DFHM_SCHED_* */
+    int32_t chunk_steps;    /* steps per resident launch / captured graph; 0 = auto */
+    double dt_s;            /* > 0 */
+    double Lv, cw;          /* 0 -> 2.5e6 J/kg, 4180 J/(kg K) */
+    double rho_a, c_pa, c_pv, Pv_ref;   /* 0 -> 1.2, 1006, 1860, 1.61e5 */
+    void *stream;           /* hipStream_t or NULL */
+    int32_t block_threads;  /* resident: threads per workgroup; 0 = autotune */
+    int32_t nodes_per_thread; /* resident: nodes per thread; 0 = autotune */
+    int32_t use_graph;      /* stream schedule: replay captured chunks (1) */
+    int32_t reserved;
+} dfhm_config;
+
+/* Device bytes the wall state of a batch needs (levels, node layer ids,
+ * descriptors, flux state, tile tables).  Pass at least this much as the
+ * arena of dfhm_create to keep all wall state in caller-owned memory. */
+size_t dfhm_arena_bytes(const dfhm_config *cfg, const dfhm_wall *walls, int64_t n_walls);
+
+/* Create a batch of n_walls >= 1 walls at their initial state (step index 0).
+ * arena: caller-owned device memory of arena_bytes (e.g. a torch tensor) that
+ * must outlive the context and is never freed by the library; NULL = the
+ * library allocates and frees its own.  Errors: DFHM_E_INVAL on a bad
+ * descriptor (nx, n_layers, thickness <= 0, negative coefficients, dt <= 0),
+ * DFHM_E_NOMEM, DFHM_E_DEVICE.  *out is set only on success. */
+dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t n_walls,
+                        void *arena, size_t arena_bytes, dfhm_ctx **out);
+
+/* Couple walls to n_rooms zones (Sec. 5.1-5.3): wall_room[w] = zone index or
+ * -1, room_side[w] = 0 | 1 the side facing that zone.  Each step the walls
+ * see the zone air of level n on that side and the zone is advanced by
+ * forward Euler with the level-n surface values (eq. wbse_tn_exp).  Allowed
+ * only at step index 0, once.  DFHM_E_UNSTABLE if a zone's explicit step
+ * fails a_T dt < 1 or a_M dt < 1, with a_T = (sum A h_T + g_v c_ma) /
+ * (rho_a V c_ma) and a_M = (sum A h_M + g_v / Pv_ref) Pv_ref / (rho_a V). */
+dfhm_status dfhm_room_couple(dfhm_ctx *ctx, const dfhm_room *rooms, int64_t n_rooms,
+                             const int64_t *wall_room, const int8_t *room_side);
+
+/* Queue n_steps >= 0 time steps (asynchronous on the context stream). */
+dfhm_status dfhm_step_n(dfhm_ctx *ctx, int64_t n_steps);
+
+/* Wait for queued work; DFHM_E_NONFINITE if a finished step produced a
+ * non-finite value (the context then latches DFHM_E_STATE). */
+dfhm_status dfhm_sync(dfhm_ctx *ctx);
+
+/* Surface fluxes, host arrays [n_walls][2 sides][2 fields (heat, vapour)]:
+ * now = the flux applied by the most recent step (DF-averaged surface value,
+ * ambient at t^n; for the forward-Euler start-up step the mean over its
+ * sub-steps); integral = dt * sum over completed steps, Neumaier-compensated
+ * in FP64 (J/m2, kg/m2).  Either pointer may be NULL.  Synchronises. */
+dfhm_status dfhm_fluxes(dfhm_ctx *ctx, double *now, double *integral);
+
+/* Fields of one wall at level 0 (= t^n) or 1 (= t^{n-1}) as FP64 host arrays
+ * of nx values (absolute K and Pa, also on the FP32 path).  Synchronises. */
+dfhm_status dfhm_get_fields(dfhm_ctx *ctx, int64_t wall, int level, double *T, double *Pv);
+/* All walls concatenated in wall order (sum of nx values each). */
+dfhm_status dfhm_get_all_fields(dfhm_ctx *ctx, int level, double *T, double *Pv);
+/* Overwrite one wall's level (0 or 1); clears a latched non-finite state. */
+dfhm_status dfhm_set_fields(dfhm_ctx *ctx, int64_t wall, int level, const double *T,
+                            const double *Pv);
+/* Set the step index (with dfhm_set_fields: restart from two given levels;
+ * n >= 1 makes the next step a DF step). */
+dfhm_status dfhm_set_step_index(dfhm_ctx *ctx, int64_t n);
+
+/* Zone air at level n: Ta [K], Pva [Pa], host arrays of n_rooms. */
+dfhm_status dfhm_get_rooms(dfhm_ctx *ctx, double *Ta, double *Pva);
+
+/* Resolved launch configuration (after autotuning). */
+typedef struct {
+    int32_t schedule, precision, block_threads, nodes_per_thread;
+    int32_t chunk_steps, n_blocks, max_walls_per_block, use_graph;
+    int64_t n_walls, n_rooms, total_nodes, step_index;
+    double pack_efficiency;   /* useful nodes / node slots of the resident packing */
+} dfhm_info;
+dfhm_status dfhm_get_info(const dfhm_ctx *ctx, dfhm_info *info);
+
+/* Choose the schedule and resident launch shape by timing candidate kernels
+ * on a copy of the batch for `probe_steps` steps each (state unchanged).  The
+ * result is cached per (device, precision, schedule candidates, size
+ * bucket) in the file named by the DFHM_AUTOTUNE_CACHE environment variable
+ * when it is set.  Allowed only at step index 0 or after a completed step. */
+dfhm_status dfhm_autotune(dfhm_ctx *ctx, int32_t probe_steps);
+
+int64_t dfhm_step_index(const dfhm_ctx *ctx);
+const char *dfhm_last_error(const dfhm_ctx *ctx);
+const char *dfhm_status_string(dfhm_status s);
+void dfhm_destroy(dfhm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFHM_H */

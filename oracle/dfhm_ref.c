@@ -412,11 +412,15 @@ static double ftcs_bound(const ref_wall *w, const int *lay, const double *T,
     return best;
 }
 
-/* Number of forward-Euler sub-steps for the start-up step. */
+/* Number of forward-Euler sub-steps for the start-up step: ceil(2 dt / b),
+ * at least 1 and at most 2^20 (a zero or non-finite bound gives 1 or the cap). */
+#define REF_MAX_SUBSTEPS ((int64_t)1 << 20)
 static int64_t ftcs_substeps(double dt, double bound)
 {
     double m = ceil(2.0 * dt / bound);
-    return m < 1.0 ? 1 : (int64_t)m;
+    if (!(m >= 1.0)) return 1;
+    if (m > (double)REF_MAX_SUBSTEPS) return REF_MAX_SUBSTEPS;
+    return (int64_t)m;
 }
 
 /*

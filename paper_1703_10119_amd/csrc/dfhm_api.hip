@@ -1,0 +1,1167 @@
+// dfhm_api.hip -- host runtime behind include/dfhm.h.
+//
+// The host only validates descriptors, lays out device memory, packs walls
+// into workgroups and enqueues kernels; every step of the method (grid
+// constants, layer ids, start-up, DF updates, fluxes, zone balance) runs on
+// the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dfhm.h"
+#include "df_kernels.hpp"
+#include "df_resident.hpp"
+
+using namespace dfhm;
+
+struct dfhm_ctx {
+    dfhm_config cfg{};
+    RunConst rc{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t nw = 0, nr = 0, N = 0;
+    int64_t n = 0;                 // host copy of the step index
+    int precision = DFHM_FP64;
+    size_t esize = 8;
+    // device memory
+    bool own_arena = false;
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    WallDev *d_walls = nullptr;
+    int2 *d_tiles = nullptr;
+    int ntiles = 0;
+    void *d_T[2] = {nullptr, nullptr};
+    void *d_P[2] = {nullptr, nullptr};
+    uint8_t *d_lay = nullptr;
+    double *d_flux = nullptr;
+    int *d_bad = nullptr;
+    int64_t *d_step = nullptr;
+    // zones
+    void *room_mem = nullptr;
+    RoomDev *d_rooms = nullptr;
+    int32_t *d_room_walls = nullptr;
+    double *d_roomT = nullptr, *d_roomP = nullptr, *d_go = nullptr, *d_qh = nullptr;
+    // resident packing
+    void *pack_mem = nullptr;
+    ResBlock *d_blocks = nullptr;
+    int32_t *d_block_walls = nullptr;
+    int32_t *d_block_rooms = nullptr;
+    int n_blocks = 0, max_wpb = 0;
+    double pack_eff = 0.0;
+    int res_threads = 0, res_npt = 0;
+    bool packed = false;
+    // captured chunk of streaming steps
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = 0;
+    // law shape shared by all walls (required by the resident kernel)
+    bool shape_uniform = false;
+    Shape shape{};
+    int max_group_nodes = 0;
+    // autotuned choice
+    bool tuned = false;
+    int tuned_sched = DFHM_SCHED_RESIDENT;
+    // host copies
+    std::vector<WallDev> walls;
+    std::vector<int64_t> wall_room;
+    std::vector<int8_t> room_side;
+    std::string err;
+    dfhm_status latched = DFHM_OK;
+};
+
+namespace {
+
+dfhm_status fail(dfhm_ctx *c, dfhm_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), DFHM_E_DEVICE,                                               \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t walls, tiles, T0, T1, P0, P1, lay, flux, bad, step, total;
+};
+
+int count_tiles(const dfhm_wall *w, int64_t nw)
+{
+    int64_t t = 0;
+    for (int64_t i = 0; i < nw; ++i) t += (w[i].nx + kStreamTile - 1) / kStreamTile;
+    return (int)t;
+}
+
+Layout layout_of(int precision, const dfhm_wall *w, int64_t nw)
+{
+    size_t es = precision == DFHM_FP32 ? 4 : 8;
+    int64_t N = 0;
+    for (int64_t i = 0; i < nw; ++i) N += w[i].nx;
+    Layout L{};
+    size_t o = 0;
+    L.walls = o; o = align256(o + sizeof(WallDev) * nw);
+    L.tiles = o; o = align256(o + sizeof(int2) * (size_t)count_tiles(w, nw));
+    L.T0 = o; o = align256(o + es * N);
+    L.T1 = o; o = align256(o + es * N);
+    L.P0 = o; o = align256(o + es * N);
+    L.P1 = o; o = align256(o + es * N);
+    L.lay = o; o = align256(o + (size_t)N);
+    L.flux = o; o = align256(o + sizeof(double) * 12 * nw);
+    L.bad = o; o = align256(o + sizeof(int));
+    L.step = o; o = align256(o + sizeof(int64_t));
+    L.total = o;
+    return L;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+std::string check_wall(const dfhm_wall &w, int64_t i)
+{
+    char b[160];
+    if (w.nx < 3 || w.nx > kMaxNx) {
+        snprintf(b, sizeof b, "wall %lld: nx=%d outside [3, %d]", (long long)i, w.nx, kMaxNx);
+        return b;
+    }
+    if (w.n_layers < 1 || w.n_layers > kMaxLayers) {
+        snprintf(b, sizeof b, "wall %lld: n_layers=%d outside [1, 3]", (long long)i, w.n_layers);
+        return b;
+    }
+    for (int l = 0; l < w.n_layers; ++l) {
+        const dfhm_layer &m = w.layer[l];
+        if (!(std::isfinite(m.thickness_m) && m.thickness_m > 0.0) || !finite_nonneg(m.k0) ||
+            !finite_nonneg(m.kM0) || !(std::isfinite(m.c0) && m.c0 > 0.0) ||
+            !(std::isfinite(m.cM0) && m.cM0 > 0.0) || !std::isfinite(m.a_T) ||
+            !std::isfinite(m.a_M) || !std::isfinite(m.b_TM) || !std::isfinite(m.c_T) ||
+            !std::isfinite(m.c_M) || !std::isfinite(m.e_TM) || !std::isfinite(m.f_TM)) {
+            snprintf(b, sizeof b, "wall %lld layer %d: bad thickness or coefficients",
+                     (long long)i, l);
+            return b;
+        }
+    }
+    for (int s = 0; s < 2; ++s) {
+        if (!finite_nonneg(w.h_T[s]) || !finite_nonneg(w.h_M[s]) || !std::isfinite(w.q_inf[s]) ||
+            !std::isfinite(w.g_inf[s])) {
+            snprintf(b, sizeof b, "wall %lld side %d: bad surface coefficients", (long long)i, s);
+            return b;
+        }
+        const dfhm_sine *ss[2] = {&w.T_amb[s], &w.RH_amb[s]};
+        for (const dfhm_sine *q : ss)
+            if (!(std::isfinite(q->period_s) && q->period_s > 0.0) || !std::isfinite(q->mean) ||
+                !std::isfinite(q->amp) || !std::isfinite(q->phase)) {
+                snprintf(b, sizeof b, "wall %lld side %d: bad ambient sinusoid", (long long)i, s);
+                return b;
+            }
+    }
+    if (!(std::isfinite(w.T0) && w.T0 > 0.0) || !(std::isfinite(w.RH0) && w.RH0 > 0.0) ||
+        !finite_nonneg(w.area_m2)) {
+        snprintf(b, sizeof b, "wall %lld: bad initial state or area", (long long)i);
+        return b;
+    }
+    return "";
+}
+
+void fill_wall(WallDev &d, const dfhm_wall &w, int32_t off)
+{
+    std::memset(&d, 0, sizeof d);
+    d.off = off;
+    d.nx = w.nx;
+    d.n_layers = w.n_layers;
+    d.room = -1;
+    d.room_side = 1;
+    d.area = w.area_m2;
+    d.T0 = w.T0;
+    d.RH0 = w.RH0;
+    for (int s = 0; s < 2; ++s) {
+        d.hT[s] = w.h_T[s];
+        d.hM[s] = w.h_M[s];
+        d.qinf[s] = w.q_inf[s];
+        d.ginf[s] = w.g_inf[s];
+        const dfhm_sine &a = w.T_amb[s], &b = w.RH_amb[s];
+        d.Tamb[s][0] = a.mean; d.Tamb[s][1] = a.amp; d.Tamb[s][2] = a.period_s; d.Tamb[s][3] = a.phase;
+        d.RHamb[s][0] = b.mean; d.RHamb[s][1] = b.amp; d.RHamb[s][2] = b.period_s; d.RHamb[s][3] = b.phase;
+    }
+    for (int l = 0; l < kMaxLayers; ++l) {
+        const dfhm_layer &m = w.layer[l];
+        double *p = d.lay[l];
+        if (l >= w.n_layers) {
+            // unused slots mirror layer 0 so that no lane ever reads garbage
+            std::memcpy(p, d.lay[0], sizeof(double) * L_COUNT);
+            continue;
+        }
+        p[L_THICK] = m.thickness_m; p[L_K0] = m.k0; p[L_AT] = m.a_T; p[L_KM0] = m.kM0;
+        p[L_AM] = m.a_M; p[L_BTM] = m.b_TM; p[L_C0] = m.c0; p[L_CT] = m.c_T;
+        p[L_CM0] = m.cM0; p[L_AC] = m.c_M; p[L_ETM] = m.e_TM; p[L_FTM] = m.f_TM;
+    }
+}
+
+double orz(double v, double d) { return v == 0.0 ? d : v; }
+
+dfhm_status check_bad(dfhm_ctx *c)
+{
+    int bad = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (bad) {
+        c->latched = DFHM_E_STATE;
+        return fail(c, DFHM_E_NONFINITE, "a step produced a non-finite value");
+    }
+    return DFHM_OK;
+}
+
+template <typename R>
+dfhm_status launch_stream_step(dfhm_ctx *c, int off)
+{
+    hipLaunchKernelGGL(k_df_stream<R>, dim3(c->ntiles), dim3(kStreamBlock), 0, c->stream,
+                       c->d_walls, c->d_tiles, (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0],
+                       (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_flux, c->d_bad,
+                       c->d_step, off, c->rc);
+    return DFHM_OK;
+}
+
+template <typename R>
+dfhm_status launch_room_step(dfhm_ctx *c, int off)
+{
+    if (c->nr == 0) return DFHM_OK;
+    int nb = (int)((c->nr + 63) / 64);
+    hipLaunchKernelGGL(k_room_step<R>, dim3(nb), dim3(64), 0, c->stream, c->d_rooms,
+                       c->d_room_walls, c->d_walls, (const R *)c->d_T[0], (const R *)c->d_T[1],
+                       (const R *)c->d_P[0], (const R *)c->d_P[1], c->d_roomT, c->d_roomP,
+                       c->d_go, c->d_qh, (int)c->nr, c->d_step, off, c->rc);
+    return DFHM_OK;
+}
+
+template <typename R>
+dfhm_status launch_startup(dfhm_ctx *c)
+{
+    hipLaunchKernelGGL(k_startup<R>, dim3((unsigned)c->nw), dim3(kStartBlock), 0, c->stream,
+                       c->d_walls, (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0],
+                       (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_flux, c->d_bad,
+                       c->rc);
+    return DFHM_OK;
+}
+
+void tick(dfhm_ctx *c, int k)
+{
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, c->stream, c->d_step, k);
+}
+
+// Enqueue `k` streaming steps starting at host step c->n (n >= 1, or n == 0
+// with the repeat start), with one device tick at the end.
+template <typename R>
+void enqueue_stream_chunk(dfhm_ctx *c, int k)
+{
+    for (int i = 0; i < k; ++i) {
+        launch_stream_step<R>(c, i);
+        launch_room_step<R>(c, i);
+    }
+    tick(c, k);
+}
+
+template <typename R>
+dfhm_status step_stream(dfhm_ctx *c, int64_t nsteps)
+{
+    while (nsteps > 0) {
+        if (c->n == 0 && c->cfg.startup == DFHM_START_FTCS) {
+            launch_startup<R>(c);
+            launch_room_step<R>(c, 0);
+            tick(c, 1);
+            c->n += 1;
+            nsteps -= 1;
+            continue;
+        }
+        int chunk = c->cfg.chunk_steps > 0 ? c->cfg.chunk_steps : 100;
+        if (c->cfg.use_graph && nsteps >= chunk) {
+            if (!c->graph_exec || c->graph_steps != chunk) {
+                if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+                if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+                HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                enqueue_stream_chunk<R>(c, chunk);
+                HIP_TRY(c, hipStreamEndCapture(c->stream, &c->graph));
+                HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+                c->graph_steps = chunk;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+            c->n += chunk;
+            nsteps -= chunk;
+            continue;
+        }
+        int k = (int)std::min<int64_t>(nsteps, chunk);
+        if (c->n == 0) k = 1;   // repeat start: the first step on its own
+        enqueue_stream_chunk<R>(c, k);
+        HIP_TRY(c, hipGetLastError());
+        c->n += k;
+        nsteps -= k;
+    }
+    return DFHM_OK;
+}
+
+// ----------------------------------------------------------- resident path
+
+struct Cand { int nt, npt; };
+// launch shapes the library is built for (threads, nodes per lane)
+const Cand kCands[] = {{256, 4}, {128, 8}, {256, 2}, {512, 2}, {128, 4}, {512, 4}, {256, 8}, {512, 8}};
+
+int effective_schedule(const dfhm_ctx *c)
+{
+    if (c->cfg.schedule != DFHM_SCHED_AUTO) return c->cfg.schedule;
+    if (c->tuned) return c->tuned_sched;
+    return c->shape_uniform ? DFHM_SCHED_RESIDENT : DFHM_SCHED_STREAM;
+}
+
+// Groups that must share a workgroup: a zone with all of its walls, or one
+// wall.  Returns the largest group size in nodes and in walls.
+void groups_of(const dfhm_ctx *c, std::vector<std::vector<int32_t>> &groups)
+{
+    groups.clear();
+    std::vector<int64_t> first(c->nr, -1);
+    for (int64_t w = 0; w < c->nw; ++w) {
+        int64_t r = c->wall_room[w];
+        if (r < 0) { groups.push_back({(int32_t)w}); continue; }
+        if (first[r] < 0) { first[r] = (int64_t)groups.size(); groups.push_back({}); }
+        groups[first[r]].push_back((int32_t)w);
+    }
+}
+
+dfhm_status pack(dfhm_ctx *c, int nt, int npt)
+{
+    const int cap = nt * npt;
+    std::vector<std::vector<int32_t>> groups;
+    groups_of(c, groups);
+    std::vector<int> gsize(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        int s = 0;
+        for (int32_t w : groups[g]) s += c->walls[w].nx;
+        gsize[g] = s;
+        if (s > cap)
+            return fail(c, DFHM_E_INVAL, "a wall or zone group of " + std::to_string(s) +
+                                             " nodes exceeds the workgroup capacity " + std::to_string(cap));
+        if ((int)groups[g].size() > kResMaxWalls)
+            return fail(c, DFHM_E_INVAL, "a zone has more walls than a workgroup holds");
+    }
+    std::vector<int> order(groups.size());
+    for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return gsize[a] > gsize[b]; });
+    // best-fit decreasing: smallest remaining capacity that still fits
+    struct Bin { int used, walls, rooms; std::vector<int> gs; };
+    std::vector<Bin> bins;
+    std::multimap<int, int> free_cap;   // remaining -> bin
+    for (int g : order) {
+        const int need = gsize[g];
+        const int gw = (int)groups[g].size();
+        const int gr = c->wall_room[groups[g][0]] >= 0 ? 1 : 0;
+        int chosen = -1;
+        for (auto it = free_cap.lower_bound(need); it != free_cap.end(); ++it) {
+            Bin &b = bins[it->second];
+            if (b.walls + gw <= kResMaxWalls && b.rooms + gr <= kResMaxRooms) {
+                chosen = it->second;
+                free_cap.erase(it);
+                break;
+            }
+        }
+        if (chosen < 0) {
+            chosen = (int)bins.size();
+            bins.push_back({0, 0, 0, {}});
+        }
+        Bin &b = bins[chosen];
+        b.used += need;
+        b.walls += gw;
+        b.rooms += gr;
+        b.gs.push_back(g);
+        if (cap - b.used > 0) free_cap.emplace(cap - b.used, chosen);
+    }
+    std::vector<ResBlock> blocks(bins.size());
+    std::vector<int32_t> bw, br;
+    int maxw = 0;
+    for (size_t i = 0; i < bins.size(); ++i) {
+        std::vector<int32_t> ws;
+        std::vector<int32_t> rs;
+        for (int g : bins[i].gs) {
+            for (int32_t w : groups[g]) ws.push_back(w);
+            int64_t r = c->wall_room[groups[g][0]];
+            if (r >= 0) rs.push_back((int32_t)r);
+        }
+        std::sort(ws.begin(), ws.end());
+        std::sort(rs.begin(), rs.end());
+        ResBlock &B = blocks[i];
+        B.w_begin = (int32_t)bw.size();
+        bw.insert(bw.end(), ws.begin(), ws.end());
+        B.w_end = (int32_t)bw.size();
+        B.r_begin = (int32_t)br.size();
+        br.insert(br.end(), rs.begin(), rs.end());
+        B.r_end = (int32_t)br.size();
+        B.n_nodes = bins[i].used;
+        B.pad = 0;
+        maxw = std::max(maxw, (int)ws.size());
+    }
+    if (br.empty()) br.push_back(0);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    size_t ob = take(sizeof(ResBlock) * blocks.size());
+    size_t ow = take(sizeof(int32_t) * bw.size());
+    size_t orr = take(sizeof(int32_t) * br.size());
+    if (c->pack_mem) { (void)hipStreamSynchronize(c->stream); (void)hipFree(c->pack_mem); c->pack_mem = nullptr; }
+    void *mem = nullptr;
+    if (hipMalloc(&mem, o) != hipSuccess) return fail(c, DFHM_E_NOMEM, "packing tables");
+    c->pack_mem = mem;
+    c->d_blocks = (ResBlock *)((char *)mem + ob);
+    c->d_block_walls = (int32_t *)((char *)mem + ow);
+    c->d_block_rooms = (int32_t *)((char *)mem + orr);
+    HIP_TRY(c, hipMemcpyAsync(c->d_blocks, blocks.data(), sizeof(ResBlock) * blocks.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_block_walls, bw.data(), sizeof(int32_t) * bw.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_block_rooms, br.data(), sizeof(int32_t) * br.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->n_blocks = (int)blocks.size();
+    c->max_wpb = maxw;
+    c->pack_eff = (double)c->N / ((double)blocks.size() * cap);
+    c->res_threads = nt;
+    c->res_npt = npt;
+    c->packed = true;
+    return DFHM_OK;
+}
+
+int max_group(const dfhm_ctx *c)
+{
+    std::vector<std::vector<int32_t>> groups;
+    groups_of(c, groups);
+    int m = 0;
+    for (auto &g : groups) {
+        int s = 0;
+        for (int32_t w : g) s += c->walls[w].nx;
+        m = std::max(m, s);
+    }
+    return m;
+}
+
+// Default launch shape: the first candidate whose capacity holds the largest
+// group (nodes per lane >= 2 keeps the halo exchange small).
+Cand default_shape(const dfhm_ctx *c)
+{
+    int need = max_group(c);
+    for (const Cand &k : kCands)
+        if (k.nt * k.npt >= need) return k;
+    return {512, 8};
+}
+
+dfhm_status ensure_packing(dfhm_ctx *c)
+{
+    if (!c->shape_uniform)
+        return fail(c, DFHM_E_INVAL, "the resident schedule needs one law shape for all walls");
+    int nt = c->res_threads, npt = c->res_npt;
+    if (c->cfg.block_threads > 0 && c->cfg.nodes_per_thread > 0) {
+        nt = c->cfg.block_threads;
+        npt = c->cfg.nodes_per_thread;
+    } else if (!nt || !npt) {
+        Cand k = default_shape(c);
+        nt = k.nt;
+        npt = k.npt;
+    }
+    bool known = false;
+    for (const Cand &k : kCands) known |= (k.nt == nt && k.npt == npt);
+    if (!known) return fail(c, DFHM_E_INVAL, "unsupported resident launch shape");
+    if (c->packed && c->res_threads == nt && c->res_npt == npt) return DFHM_OK;
+    return pack(c, nt, npt);
+}
+
+template <typename R, int NPT, int NT>
+void launch_res(dfhm_ctx *c, int k)
+{
+    static bool attr_set = false;   // large shapes need more than 64 KB of LDS
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)res_dyn_lds<R>(NT));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_df_resident<R, NPT, NT>), dim3(c->n_blocks), dim3(NT), res_dyn_lds<R>(NT),
+                       c->stream, c->d_blocks, c->d_block_walls, c->d_block_rooms, c->d_walls,
+                       (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0], (R *)c->d_P[1], c->d_lay,
+                       c->d_rooms, c->d_roomT, c->d_roomP, c->d_go, c->d_qh, c->d_flux, c->d_bad,
+                       c->d_step, k, c->rc, c->shape);
+}
+
+template <typename R>
+void launch_resident(dfhm_ctx *c, int k)
+{
+    const int nt = c->res_threads, npt = c->res_npt;
+#define DFHM_RES_CASE(T_, P_) if (nt == T_ && npt == P_) { launch_res<R, P_, T_>(c, k); return; }
+    DFHM_RES_CASE(256, 4) DFHM_RES_CASE(128, 8) DFHM_RES_CASE(256, 2) DFHM_RES_CASE(512, 2)
+    DFHM_RES_CASE(128, 4) DFHM_RES_CASE(512, 4) DFHM_RES_CASE(256, 8) DFHM_RES_CASE(512, 8)
+#undef DFHM_RES_CASE
+}
+
+template <typename R>
+dfhm_status step_resident(dfhm_ctx *c, int64_t nsteps)
+{
+    while (nsteps > 0) {
+        if (c->n == 0 && c->cfg.startup == DFHM_START_FTCS) {
+            launch_startup<R>(c);
+            launch_room_step<R>(c, 0);
+            tick(c, 1);
+            HIP_TRY(c, hipGetLastError());
+            c->n += 1;
+            nsteps -= 1;
+            continue;
+        }
+        dfhm_status st = ensure_packing(c);
+        if (st) return st;
+        const int chunk = c->cfg.chunk_steps > 0 ? c->cfg.chunk_steps : 1000;
+        const int k = (int)std::min<int64_t>(nsteps, chunk);
+        launch_resident<R>(c, k);
+        tick(c, k);
+        HIP_TRY(c, hipGetLastError());
+        c->n += k;
+        nsteps -= k;
+    }
+    return DFHM_OK;
+}
+
+bool shape_of(const dfhm_wall *w, int64_t nw, Shape &sh)
+{
+    const dfhm_layer &m0 = w[0].layer[0];
+    sh = {m0.a_T, m0.a_M, m0.b_TM, m0.c_T, m0.c_M, m0.e_TM, m0.f_TM};
+    for (int64_t i = 0; i < nw; ++i)
+        for (int l = 0; l < w[i].n_layers; ++l) {
+            const dfhm_layer &m = w[i].layer[l];
+            if (m.a_T != sh.aT || m.a_M != sh.aM || m.b_TM != sh.bTM || m.c_T != sh.cT ||
+                m.c_M != sh.aC || m.e_TM != sh.eTM || m.f_TM != sh.fTM)
+                return false;
+        }
+    return true;
+}
+
+} // namespace
+
+// ===================================================================== API
+
+extern "C" {
+
+const char *dfhm_status_string(dfhm_status s)
+{
+    switch (s) {
+    case DFHM_OK: return "ok";
+    case DFHM_E_INVAL: return "invalid argument";
+    case DFHM_E_NOMEM: return "out of device memory";
+    case DFHM_E_DEVICE: return "device error";
+    case DFHM_E_NONFINITE: return "non-finite state";
+    case DFHM_E_STATE: return "invalid state";
+    case DFHM_E_UNSTABLE: return "unstable explicit zone step";
+    }
+    return "unknown";
+}
+
+size_t dfhm_arena_bytes(const dfhm_config *cfg, const dfhm_wall *walls, int64_t n_walls)
+{
+    if (!cfg || !walls || n_walls < 1) return 0;
+    return layout_of(cfg->precision, walls, n_walls).total;
+}
+
+dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t n_walls,
+                        void *arena, size_t arena_bytes, dfhm_ctx **out)
+{
+    if (!out) return DFHM_E_INVAL;
+    *out = nullptr;
+    if (!cfg || !walls || n_walls < 1) return DFHM_E_INVAL;
+    if (!(std::isfinite(cfg->dt_s) && cfg->dt_s > 0.0)) return DFHM_E_INVAL;
+    if (cfg->precision != DFHM_FP64 && cfg->precision != DFHM_FP32) return DFHM_E_INVAL;
+    if (cfg->startup != DFHM_START_FTCS && cfg->startup != DFHM_START_REPEAT) return DFHM_E_INVAL;
+    if (cfg->schedule < DFHM_SCHED_AUTO || cfg->schedule > DFHM_SCHED_RESIDENT) return DFHM_E_INVAL;
+    if (cfg->chunk_steps < 0 || cfg->block_threads < 0 || cfg->nodes_per_thread < 0) return DFHM_E_INVAL;
+    int64_t N = 0;
+    for (int64_t i = 0; i < n_walls; ++i) {
+        if (!check_wall(walls[i], i).empty()) return DFHM_E_INVAL;
+        N += walls[i].nx;
+    }
+    if (N >= (int64_t(1) << 31)) return DFHM_E_INVAL;
+    Layout L = layout_of(cfg->precision, walls, n_walls);
+    if (arena && arena_bytes < L.total) return DFHM_E_NOMEM;
+
+    dfhm_ctx *c = new (std::nothrow) dfhm_ctx();
+    if (!c) return DFHM_E_NOMEM;
+    c->cfg = *cfg;
+    c->precision = cfg->precision;
+    c->esize = cfg->precision == DFHM_FP32 ? 4 : 8;
+    c->stream = (hipStream_t)cfg->stream;
+    c->nw = n_walls;
+    c->N = N;
+    c->rc.dt = cfg->dt_s;
+    c->rc.Lv = orz(cfg->Lv, 2.5e6);
+    c->rc.cw = orz(cfg->cw, 4180.0);
+    c->rc.rho_a = orz(cfg->rho_a, 1.2);
+    c->rc.c_pa = orz(cfg->c_pa, 1006.0);
+    c->rc.c_pv = orz(cfg->c_pv, 1860.0);
+    c->rc.Pv_ref = orz(cfg->Pv_ref, 1.61e5);
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return DFHM_E_DEVICE; }
+
+    if (arena) {
+        c->arena = arena;
+        c->arena_bytes = arena_bytes;
+    } else {
+        if (hipMalloc(&c->arena, L.total) != hipSuccess) { delete c; return DFHM_E_NOMEM; }
+        c->own_arena = true;
+        c->arena_bytes = L.total;
+    }
+    char *base = (char *)c->arena;
+    c->d_walls = (WallDev *)(base + L.walls);
+    c->d_tiles = (int2 *)(base + L.tiles);
+    c->d_T[0] = base + L.T0; c->d_T[1] = base + L.T1;
+    c->d_P[0] = base + L.P0; c->d_P[1] = base + L.P1;
+    c->d_lay = (uint8_t *)(base + L.lay);
+    c->d_flux = (double *)(base + L.flux);
+    c->d_bad = (int *)(base + L.bad);
+    c->d_step = (int64_t *)(base + L.step);
+
+    c->walls.resize(n_walls);
+    std::vector<int2> tiles;
+    tiles.reserve(count_tiles(walls, n_walls));
+    int32_t off = 0;
+    for (int64_t i = 0; i < n_walls; ++i) {
+        fill_wall(c->walls[i], walls[i], off);
+        for (int j0 = 0; j0 < walls[i].nx; j0 += kStreamTile) tiles.push_back(make_int2((int)i, j0));
+        off += walls[i].nx;
+    }
+    c->ntiles = (int)tiles.size();
+    c->wall_room.assign(n_walls, -1);
+    c->room_side.assign(n_walls, 1);
+    c->shape_uniform = shape_of(walls, n_walls, c->shape);
+    if (cfg->schedule == DFHM_SCHED_RESIDENT && !c->shape_uniform) {
+        delete c;
+        return DFHM_E_INVAL;
+    }
+
+    auto bail = [&](dfhm_status s) {
+        dfhm_destroy(c);
+        return s;
+    };
+    std::vector<double> zeros(12 * n_walls, 0.0);
+    int zero = 0;
+    int64_t zero64 = 0;
+    if (hipMemcpyAsync(c->d_walls, c->walls.data(), sizeof(WallDev) * n_walls,
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_flux, zeros.data(), sizeof(double) * zeros.size(),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_bad, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_step, &zero64, sizeof(int64_t), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return bail(DFHM_E_DEVICE);
+    hipLaunchKernelGGL(k_init_walls, dim3((unsigned)((n_walls + 63) / 64)), dim3(64), 0, c->stream,
+                       c->d_walls, (int)n_walls, c->rc.dt);
+    if (c->precision == DFHM_FP64)
+        hipLaunchKernelGGL(k_init_nodes<double>, dim3(c->ntiles), dim3(kStreamBlock), 0, c->stream,
+                           c->d_walls, c->d_tiles, c->d_lay, (double *)c->d_T[0], (double *)c->d_T[1],
+                           (double *)c->d_P[0], (double *)c->d_P[1]);
+    else
+        hipLaunchKernelGGL(k_init_nodes<float>, dim3(c->ntiles), dim3(kStreamBlock), 0, c->stream,
+                           c->d_walls, c->d_tiles, c->d_lay, (float *)c->d_T[0], (float *)c->d_T[1],
+                           (float *)c->d_P[0], (float *)c->d_P[1]);
+    if (hipGetLastError() != hipSuccess) return bail(DFHM_E_DEVICE);
+    // keep the device-computed grid constants and initial vapour pressure
+    if (hipMemcpyAsync(c->walls.data(), c->d_walls, sizeof(WallDev) * n_walls,
+                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return bail(DFHM_E_DEVICE);
+    *out = c;
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_rooms,
+                             const int64_t *wall_room, const int8_t *room_side)
+{
+    if (!c) return DFHM_E_INVAL;
+    if (c->n != 0 || c->nr != 0) return fail(c, DFHM_E_STATE, "zones must be coupled once, at step 0");
+    if (!rooms || n_rooms < 1 || !wall_room || !room_side)
+        return fail(c, DFHM_E_INVAL, "rooms, wall_room and room_side are required");
+    for (int64_t w = 0; w < c->nw; ++w) {
+        if (wall_room[w] < -1 || wall_room[w] >= n_rooms)
+            return fail(c, DFHM_E_INVAL, "wall_room index out of range");
+        if (wall_room[w] >= 0 && room_side[w] != 0 && room_side[w] != 1)
+            return fail(c, DFHM_E_INVAL, "room_side must be 0 or 1");
+    }
+    int64_t total_sched = 0;
+    for (int64_t r = 0; r < n_rooms; ++r) {
+        const dfhm_room &m = rooms[r];
+        if (!(m.volume_m3 > 0.0) || !(m.ach_per_h >= 0.0) || !(m.T0 > 0.0) || !(m.RH0 > 0.0) ||
+            m.n_sched < 1 || !(m.sched_dt_s > 0.0) || !m.g_o_kg_s || !m.Q_h_W ||
+            !(m.T_out.period_s > 0.0) || !(m.RH_out.period_s > 0.0))
+            return fail(c, DFHM_E_INVAL, "bad zone descriptor " + std::to_string(r));
+        total_sched += m.n_sched;
+    }
+    // room -> walls lists in ascending wall order
+    std::vector<std::vector<int32_t>> lists(n_rooms);
+    for (int64_t w = 0; w < c->nw; ++w)
+        if (wall_room[w] >= 0) lists[wall_room[w]].push_back((int32_t)w);
+    // explicit zone step stability (forward Euler): a dt < 1 for both fields
+    const RunConst &rc = c->rc;
+    for (int64_t r = 0; r < n_rooms; ++r) {
+        const dfhm_room &m = rooms[r];
+        double mass = rc.rho_a * m.volume_m3;
+        double gv = m.ach_per_h * mass / 3600.0;
+        double Pa0 = m.RH0 * 610.94 * std::exp(17.625 * (m.T0 - 273.15) / (m.T0 - 273.15 + 243.04));
+        double cma = rc.c_pa + rc.c_pv * Pa0 / rc.Pv_ref;
+        double sT = gv * cma, sM = gv / rc.Pv_ref;
+        for (int32_t w : lists[r]) {
+            const WallDev &W = c->walls[w];
+            int side = room_side[w];
+            sT += W.area * W.hT[side];
+            sM += W.area * W.hM[side];
+        }
+        double aT = sT / (mass * cma), aM = sM / (mass / rc.Pv_ref);
+        if (!(aT * rc.dt < 1.0) || !(aM * rc.dt < 1.0)) {
+            char b[200];
+            snprintf(b, sizeof b, "zone %lld: explicit step unstable (a_T dt = %.3g, a_M dt = %.3g)",
+                     (long long)r, aT * rc.dt, aM * rc.dt);
+            return fail(c, DFHM_E_UNSTABLE, b);
+        }
+    }
+    std::vector<RoomDev> rd(n_rooms);
+    std::vector<int32_t> rw;
+    std::vector<double> go(total_sched), qh(total_sched), Ta(n_rooms), Pa(n_rooms);
+    int32_t so = 0;
+    for (int64_t r = 0; r < n_rooms; ++r) {
+        const dfhm_room &m = rooms[r];
+        RoomDev &d = rd[r];
+        std::memset(&d, 0, sizeof d);
+        d.volume = m.volume_m3; d.ach = m.ach_per_h; d.T0 = m.T0; d.RH0 = m.RH0;
+        d.Tout[0] = m.T_out.mean; d.Tout[1] = m.T_out.amp; d.Tout[2] = m.T_out.period_s; d.Tout[3] = m.T_out.phase;
+        d.RHout[0] = m.RH_out.mean; d.RHout[1] = m.RH_out.amp; d.RHout[2] = m.RH_out.period_s; d.RHout[3] = m.RH_out.phase;
+        d.sched_dt = m.sched_dt_s;
+        d.n_sched = m.n_sched;
+        d.sched_off = so;
+        std::memcpy(&go[so], m.g_o_kg_s, sizeof(double) * m.n_sched);
+        std::memcpy(&qh[so], m.Q_h_W, sizeof(double) * m.n_sched);
+        so += m.n_sched;
+        d.w_begin = (int32_t)rw.size();
+        for (int32_t w : lists[r]) rw.push_back(w);
+        d.w_end = (int32_t)rw.size();
+        Ta[r] = m.T0;
+        Pa[r] = m.RH0;   // converted to Pv on the device
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    size_t o_rooms = take(sizeof(RoomDev) * n_rooms);
+    size_t o_rw = take(sizeof(int32_t) * std::max<size_t>(rw.size(), 1));
+    size_t o_T = take(sizeof(double) * n_rooms);
+    size_t o_P = take(sizeof(double) * n_rooms);
+    size_t o_go = take(sizeof(double) * total_sched);
+    size_t o_qh = take(sizeof(double) * total_sched);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, o) != hipSuccess) return fail(c, DFHM_E_NOMEM, "zone buffers");
+    char *b = (char *)mem;
+    c->room_mem = mem;
+    c->d_rooms = (RoomDev *)(b + o_rooms);
+    c->d_room_walls = (int32_t *)(b + o_rw);
+    c->d_roomT = (double *)(b + o_T);
+    c->d_roomP = (double *)(b + o_P);
+    c->d_go = (double *)(b + o_go);
+    c->d_qh = (double *)(b + o_qh);
+    for (int64_t w = 0; w < c->nw; ++w) {
+        c->wall_room[w] = wall_room[w];
+        c->room_side[w] = wall_room[w] >= 0 ? room_side[w] : 1;
+        c->walls[w].room = (int32_t)wall_room[w];
+        c->walls[w].room_side = c->room_side[w];
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_rooms, rd.data(), sizeof(RoomDev) * n_rooms, hipMemcpyHostToDevice, c->stream));
+    if (!rw.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_room_walls, rw.data(), sizeof(int32_t) * rw.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_roomT, Ta.data(), sizeof(double) * n_rooms, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_roomP, Pa.data(), sizeof(double) * n_rooms, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_go, go.data(), sizeof(double) * total_sched, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_qh, qh.data(), sizeof(double) * total_sched, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_walls, c->walls.data(), sizeof(WallDev) * c->nw, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_init_rooms, dim3((unsigned)((n_rooms + 63) / 64)), dim3(64), 0, c->stream,
+                       c->d_rooms, c->d_roomP, (int)n_rooms);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->nr = n_rooms;
+    c->packed = false;   // the resident packing must keep zones whole
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_step_n(dfhm_ctx *c, int64_t nsteps)
+{
+    if (!c) return DFHM_E_INVAL;
+    if (nsteps < 0) return fail(c, DFHM_E_INVAL, "negative step count");
+    if (c->latched != DFHM_OK) return fail(c, DFHM_E_STATE, "context holds a non-finite state");
+    if (nsteps == 0) return DFHM_OK;
+    int sched = effective_schedule(c);
+    if (sched == DFHM_SCHED_RESIDENT) {
+        return c->precision == DFHM_FP64 ? step_resident<double>(c, nsteps)
+                                          : step_resident<float>(c, nsteps);
+    }
+    return c->precision == DFHM_FP64 ? step_stream<double>(c, nsteps) : step_stream<float>(c, nsteps);
+}
+
+dfhm_status dfhm_sync(dfhm_ctx *c)
+{
+    if (!c) return DFHM_E_INVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->latched != DFHM_OK) return fail(c, DFHM_E_STATE, "context holds a non-finite state");
+    return check_bad(c);
+}
+
+dfhm_status dfhm_fluxes(dfhm_ctx *c, double *now, double *integral)
+{
+    if (!c) return DFHM_E_INVAL;
+    std::vector<double> f(12 * c->nw);
+    HIP_TRY(c, hipMemcpyAsync(f.data(), c->d_flux, sizeof(double) * f.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int64_t w = 0; w < c->nw; ++w)
+        for (int k = 0; k < 4; ++k) {
+            if (now) now[4 * w + k] = f[12 * w + k];
+            if (integral) integral[4 * w + k] = f[12 * w + 4 + k] + f[12 * w + 8 + k];
+        }
+    return DFHM_OK;
+}
+
+static dfhm_status copy_level(dfhm_ctx *c, int level, int64_t off, int64_t cnt, void *host)
+{
+    int b = (int)((c->n + (level == 0 ? 0 : 1)) & 1);
+    char *T = (char *)c->d_T[b] + c->esize * off;
+    char *P = (char *)c->d_P[b] + c->esize * off;
+    HIP_TRY(c, hipMemcpyAsync(host, T, c->esize * cnt, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync((char *)host + c->esize * cnt, P, c->esize * cnt, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DFHM_OK;
+}
+
+static void to_abs(const dfhm_ctx *c, const WallDev &W, const void *raw, int64_t cnt, int64_t at,
+                   double *T, double *P)
+{
+    if (c->precision == DFHM_FP64) {
+        const double *t = (const double *)raw;
+        std::memcpy(T, t + at, sizeof(double) * W.nx);
+        std::memcpy(P, t + cnt + at, sizeof(double) * W.nx);
+    } else {
+        const float *t = (const float *)raw;
+        double pref = (double)(float)W.P0;
+        for (int j = 0; j < W.nx; ++j) {
+            T[j] = W.T0 + (double)t[at + j];
+            P[j] = pref + (double)t[cnt + at + j];
+        }
+    }
+}
+
+dfhm_status dfhm_get_fields(dfhm_ctx *c, int64_t wall, int level, double *T, double *Pv)
+{
+    if (!c) return DFHM_E_INVAL;
+    if (wall < 0 || wall >= c->nw || (level != 0 && level != 1) || !T || !Pv)
+        return fail(c, DFHM_E_INVAL, "bad wall index, level or buffer");
+    const WallDev &W = c->walls[wall];
+    std::vector<char> raw(c->esize * 2 * W.nx);
+    dfhm_status s = copy_level(c, level, W.off, W.nx, raw.data());
+    if (s) return s;
+    to_abs(c, W, raw.data(), W.nx, 0, T, Pv);
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_get_all_fields(dfhm_ctx *c, int level, double *T, double *Pv)
+{
+    if (!c) return DFHM_E_INVAL;
+    if ((level != 0 && level != 1) || !T || !Pv) return fail(c, DFHM_E_INVAL, "bad level or buffer");
+    std::vector<char> raw(c->esize * 2 * c->N);
+    dfhm_status s = copy_level(c, level, 0, c->N, raw.data());
+    if (s) return s;
+    for (int64_t w = 0; w < c->nw; ++w) {
+        const WallDev &W = c->walls[w];
+        to_abs(c, W, raw.data(), c->N, W.off, T + W.off, Pv + W.off);
+    }
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_set_fields(dfhm_ctx *c, int64_t wall, int level, const double *T, const double *Pv)
+{
+    if (!c) return DFHM_E_INVAL;
+    if (wall < 0 || wall >= c->nw || (level != 0 && level != 1) || !T || !Pv)
+        return fail(c, DFHM_E_INVAL, "bad wall index, level or buffer");
+    const WallDev &W = c->walls[wall];
+    for (int j = 0; j < W.nx; ++j)
+        if (!std::isfinite(T[j]) || !std::isfinite(Pv[j]))
+            return fail(c, DFHM_E_INVAL, "non-finite field value");
+    int b = (int)((c->n + (level == 0 ? 0 : 1)) & 1);
+    std::vector<char> raw(c->esize * 2 * W.nx);
+    if (c->precision == DFHM_FP64) {
+        std::memcpy(raw.data(), T, 8 * W.nx);
+        std::memcpy(raw.data() + 8 * W.nx, Pv, 8 * W.nx);
+    } else {
+        float *t = (float *)raw.data();
+        double pref = (double)(float)W.P0;
+        for (int j = 0; j < W.nx; ++j) {
+            t[j] = (float)(T[j] - W.T0);
+            t[W.nx + j] = (float)(Pv[j] - pref);
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy((char *)c->d_T[b] + c->esize * W.off, raw.data(), c->esize * W.nx, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((char *)c->d_P[b] + c->esize * W.off, raw.data() + c->esize * W.nx, c->esize * W.nx, hipMemcpyHostToDevice));
+    int zero = 0;
+    HIP_TRY(c, hipMemcpy(c->d_bad, &zero, sizeof(int), hipMemcpyHostToDevice));
+    c->latched = DFHM_OK;
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_set_step_index(dfhm_ctx *c, int64_t n)
+{
+    if (!c) return DFHM_E_INVAL;
+    if (n < 0) return fail(c, DFHM_E_INVAL, "negative step index");
+    // level buffers follow the parity of n: move data if the parity changes
+    if ((n & 1) != (c->n & 1)) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        std::swap(c->d_T[0], c->d_T[1]);
+        std::swap(c->d_P[0], c->d_P[1]);
+        if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+        if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    }
+    HIP_TRY(c, hipMemcpy(c->d_step, &n, sizeof(int64_t), hipMemcpyHostToDevice));
+    c->n = n;
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_get_rooms(dfhm_ctx *c, double *Ta, double *Pva)
+{
+    if (!c) return DFHM_E_INVAL;
+    if (c->nr == 0) return fail(c, DFHM_E_STATE, "no zones coupled");
+    if (!Ta || !Pva) return fail(c, DFHM_E_INVAL, "null buffer");
+    HIP_TRY(c, hipMemcpyAsync(Ta, c->d_roomT, sizeof(double) * c->nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(Pva, c->d_roomP, sizeof(double) * c->nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_get_info(const dfhm_ctx *c, dfhm_info *info)
+{
+    if (!c || !info) return DFHM_E_INVAL;
+    std::memset(info, 0, sizeof *info);
+    int sched = effective_schedule(c);
+    info->schedule = sched;
+    info->precision = c->precision;
+    info->block_threads = sched == DFHM_SCHED_RESIDENT ? c->res_threads : kStreamBlock;
+    info->nodes_per_thread = sched == DFHM_SCHED_RESIDENT ? c->res_npt : 1;
+    info->chunk_steps = c->cfg.chunk_steps > 0 ? c->cfg.chunk_steps
+                                               : (sched == DFHM_SCHED_RESIDENT ? 1000 : 100);
+    info->n_blocks = sched == DFHM_SCHED_RESIDENT ? c->n_blocks : c->ntiles;
+    info->max_walls_per_block = c->max_wpb;
+    info->use_graph = c->cfg.use_graph;
+    info->n_walls = c->nw;
+    info->n_rooms = c->nr;
+    info->total_nodes = c->N;
+    info->step_index = c->n;
+    info->pack_efficiency = c->pack_eff;
+    return DFHM_OK;
+}
+
+int64_t dfhm_step_index(const dfhm_ctx *c) { return c ? c->n : -1; }
+
+const char *dfhm_last_error(const dfhm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void dfhm_destroy(dfhm_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->own_arena && c->arena) (void)hipFree(c->arena);
+    if (c->room_mem) (void)hipFree(c->room_mem);
+    if (c->pack_mem) (void)hipFree(c->pack_mem);
+    delete c;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------- autotune
+
+namespace {
+
+struct Snapshot {
+    void *mem = nullptr;
+    size_t lev = 0, flux = 0, rooms = 0;
+};
+
+dfhm_status snap_save(dfhm_ctx *c, Snapshot &sn)
+{
+    sn.lev = c->esize * c->N;
+    sn.flux = sizeof(double) * 12 * c->nw;
+    sn.rooms = sizeof(double) * c->nr;
+    size_t total = 4 * sn.lev + sn.flux + 2 * sn.rooms + sizeof(int64_t);
+    if (hipMalloc(&sn.mem, total) != hipSuccess) return fail(c, DFHM_E_NOMEM, "autotune snapshot");
+    char *b = (char *)sn.mem;
+    HIP_TRY(c, hipMemcpyAsync(b, c->d_T[0], sn.lev, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(b + sn.lev, c->d_T[1], sn.lev, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(b + 2 * sn.lev, c->d_P[0], sn.lev, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(b + 3 * sn.lev, c->d_P[1], sn.lev, hipMemcpyDeviceToDevice, c->stream));
+    b += 4 * sn.lev;
+    HIP_TRY(c, hipMemcpyAsync(b, c->d_flux, sn.flux, hipMemcpyDeviceToDevice, c->stream));
+    b += sn.flux;
+    if (c->nr) {
+        HIP_TRY(c, hipMemcpyAsync(b, c->d_roomT, sn.rooms, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(b + sn.rooms, c->d_roomP, sn.rooms, hipMemcpyDeviceToDevice, c->stream));
+    }
+    b += 2 * sn.rooms;
+    HIP_TRY(c, hipMemcpyAsync(b, c->d_step, sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
+    return DFHM_OK;
+}
+
+dfhm_status snap_restore(dfhm_ctx *c, const Snapshot &sn)
+{
+    char *b = (char *)sn.mem;
+    HIP_TRY(c, hipMemcpyAsync(c->d_T[0], b, sn.lev, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_T[1], b + sn.lev, sn.lev, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_P[0], b + 2 * sn.lev, sn.lev, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_P[1], b + 3 * sn.lev, sn.lev, hipMemcpyDeviceToDevice, c->stream));
+    b += 4 * sn.lev;
+    HIP_TRY(c, hipMemcpyAsync(c->d_flux, b, sn.flux, hipMemcpyDeviceToDevice, c->stream));
+    b += sn.flux;
+    if (c->nr) {
+        HIP_TRY(c, hipMemcpyAsync(c->d_roomT, b, sn.rooms, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_roomP, b + sn.rooms, sn.rooms, hipMemcpyDeviceToDevice, c->stream));
+    }
+    b += 2 * sn.rooms;
+    HIP_TRY(c, hipMemcpyAsync(c->d_step, b, sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
+    int zero = 0;
+    HIP_TRY(c, hipMemcpyAsync(c->d_bad, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DFHM_OK;
+}
+
+// Time `steps` steps of one candidate (sched, nt, npt); returns ms or < 0.
+template <typename R>
+double probe(dfhm_ctx *c, int sched, int nt, int npt, int steps)
+{
+    if (sched == DFHM_SCHED_RESIDENT) {
+        if (!c->packed || c->res_threads != nt || c->res_npt != npt)
+            if (pack(c, nt, npt) != DFHM_OK) return -1.0;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+    (void)hipEventRecord(e0, c->stream);
+    if (sched == DFHM_SCHED_RESIDENT) {
+        launch_resident<R>(c, steps);
+        tick(c, steps);
+    } else {
+        enqueue_stream_chunk<R>(c, steps);
+    }
+    (void)hipEventRecord(e1, c->stream);
+    float ms = -1.0f;
+    if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (hipGetLastError() != hipSuccess) return -1.0;
+    return ms;
+}
+
+std::string tune_key(const dfhm_ctx *c)
+{
+    hipDeviceProp_t p;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&p, c->device) == hipSuccess) arch = p.gcnArchName;
+    int64_t nb = 1;
+    while (nb < c->N) nb <<= 1;   // size bucket: next power of two of the node count
+    char b[256];
+    snprintf(b, sizeof b, "%s p%d s%d g%d n%lld r%lld", arch.c_str(), c->precision, c->cfg.schedule,
+             max_group(c), (long long)nb, (long long)(c->nr > 0));
+    for (char *q = b; *q; ++q)
+        if (*q == ' ' || *q == ':') *q = '_';
+    return b;
+}
+
+bool cache_lookup(const std::string &key, int &sched, int &nt, int &npt)
+{
+    const char *path = std::getenv("DFHM_AUTOTUNE_CACHE");
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char k[256];
+    int a, b, d;
+    bool hit = false;
+    while (std::fscanf(f, "%255s %d %d %d", k, &a, &b, &d) == 4)
+        if (key == k) { sched = a; nt = b; npt = d; hit = true; }
+    std::fclose(f);
+    return hit;
+}
+
+void cache_store(const std::string &key, int sched, int nt, int npt)
+{
+    const char *path = std::getenv("DFHM_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d\n", key.c_str(), sched, nt, npt);
+    std::fclose(f);
+}
+
+template <typename R>
+dfhm_status autotune_impl(dfhm_ctx *c, int probe_steps)
+{
+    const std::string key = tune_key(c);
+    int sched = 0, nt = 0, npt = 0;
+    if (cache_lookup(key, sched, nt, npt)) {
+        c->tuned = true;
+        c->tuned_sched = sched;
+        if (sched == DFHM_SCHED_RESIDENT) return pack(c, nt, npt);
+        return DFHM_OK;
+    }
+    Snapshot sn;
+    dfhm_status st = snap_save(c, sn);
+    if (st) return st;
+    const int need = max_group(c);
+    double best = 1e300;
+    int bs = -1, bnt = 0, bnpt = 0;
+    const bool try_stream = c->cfg.schedule != DFHM_SCHED_RESIDENT;
+    const bool try_res = c->cfg.schedule != DFHM_SCHED_STREAM && c->shape_uniform;
+    if (try_stream) {
+        (void)probe<R>(c, DFHM_SCHED_STREAM, 0, 0, 1);   // warm-up
+        snap_restore(c, sn);
+        double ms = probe<R>(c, DFHM_SCHED_STREAM, 0, 0, probe_steps);
+        snap_restore(c, sn);
+        if (ms >= 0 && ms < best) { best = ms; bs = DFHM_SCHED_STREAM; }
+    }
+    if (try_res) {
+        for (const Cand &k : kCands) {
+            if (k.nt * k.npt < need) continue;
+            // skip shapes that leave most lanes idle on the largest group
+            if (k.nt * k.npt >= 4 * std::max(need, 64)) continue;
+            (void)probe<R>(c, DFHM_SCHED_RESIDENT, k.nt, k.npt, 2);   // warm-up + packing
+            snap_restore(c, sn);
+            double ms = probe<R>(c, DFHM_SCHED_RESIDENT, k.nt, k.npt, probe_steps);
+            snap_restore(c, sn);
+            if (ms >= 0 && ms < best) { best = ms; bs = DFHM_SCHED_RESIDENT; bnt = k.nt; bnpt = k.npt; }
+        }
+    }
+    (void)hipFree(sn.mem);
+    if (bs < 0) return fail(c, DFHM_E_DEVICE, "autotune: no candidate ran");
+    c->tuned = true;
+    c->tuned_sched = bs;
+    cache_store(key, bs, bnt, bnpt);
+    if (bs == DFHM_SCHED_RESIDENT) return pack(c, bnt, bnpt);
+    return DFHM_OK;
+}
+
+} // namespace
+
+extern "C" dfhm_status dfhm_autotune(dfhm_ctx *c, int32_t probe_steps)
+{
+    if (!c) return DFHM_E_INVAL;
+    if (probe_steps < 1) return fail(c, DFHM_E_INVAL, "probe_steps must be >= 1");
+    if (c->latched != DFHM_OK) return fail(c, DFHM_E_STATE, "context holds a non-finite state");
+    if (c->cfg.block_threads > 0 && c->cfg.nodes_per_thread > 0)
+        return fail(c, DFHM_E_STATE, "launch shape fixed by the configuration");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t n_saved = c->n;
+    dfhm_status st = c->precision == DFHM_FP64 ? autotune_impl<double>(c, probe_steps)
+                                               : autotune_impl<float>(c, probe_steps);
+    c->n = n_saved;
+    return st;
+}

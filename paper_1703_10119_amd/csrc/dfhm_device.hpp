@@ -1,0 +1,137 @@
+// dfhm_device.hpp -- device-side data layout and material law of the
+// Dufort-Frankel wall / room kernels (gfx950).
+//
+// Layout in HBM (one context):
+//   walls   WallDev[W]           descriptor per wall (read with scalar loads)
+//   T, P    level buffers [2][N] of the storage type, walls concatenated;
+//           level n lives in buffer n & 1, level n-1 in the other one and
+//           level n+1 overwrites n-1 in place.  FP64 stores absolute K / Pa,
+//           FP32 stores deviations from the wall's initial (T0, Pv0).
+//   lay     uint8 [N]            layer of each node
+//   flux    double [W][12]       now[4], Neumaier sum[4], compensation[4]
+//                                (index side * 2 + field, field 0 = heat)
+//   rooms   RoomDev[R] + schedules + room air (FP64)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfhm {
+
+constexpr int kMaxLayers = 3;
+constexpr int kMaxNx = 2048;
+
+// law parameter slots of a layer (thickness first)
+enum LawSlot {
+    L_THICK = 0, L_K0, L_AT, L_KM0, L_AM, L_BTM, L_C0, L_CT, L_CM0, L_AC, L_ETM, L_FTM,
+    L_COUNT
+};
+
+struct WallDev {
+    int32_t off, nx, n_layers, room;   // room = -1 when no zone is coupled
+    int32_t room_side, pad0, pad1, pad2;
+    double dx, r, s, area;             // r = dt/dx^2, s = dt/dx (set on device)
+    double T0, RH0, P0, th0;           // initial state; P0, th0 set on device
+    double hT[2], hM[2], qinf[2], ginf[2];
+    double Tamb[2][4], RHamb[2][4];    // mean, amp, period, phase
+    double lay[kMaxLayers][L_COUNT];
+};
+
+struct RoomDev {
+    double volume, ach, T0, RH0;
+    double Tout[4], RHout[4];
+    double sched_dt;
+    int32_t n_sched, sched_off;        // offset into the schedule arrays
+    int32_t w_begin, w_end;            // range in the room -> wall index list
+};
+
+// Global constants of a run (kernel argument).
+struct RunConst {
+    double dt, Lv, cw, rho_a, c_pa, c_pv, Pv_ref;
+};
+
+__device__ __forceinline__ double dpi() { return 3.14159265358979323846; }
+
+// Magnus saturation pressure from theta = T - 273.15 (degC).
+__device__ __forceinline__ double psat_th(double th)
+{
+    return 610.94 * exp(17.625 * th / (th + 243.04));
+}
+__device__ __forceinline__ float psat_th(float th)
+{
+    return 610.94f * __expf(17.625f * th / (th + 243.04f));
+}
+
+__device__ __forceinline__ double sine_at(const double *s, double t)
+{
+    return s[0] + s[1] * sin(2.0 * dpi() * t / s[2] + s[3]);
+}
+
+template <typename R> struct KCoef { R kT, kM, kX; };
+template <typename R> struct CCoef { R cT, cM, cX; };
+
+template <typename R>
+__device__ __forceinline__ KCoef<R> law_k(const double *m, R phi)
+{
+    KCoef<R> k;
+    k.kT = (R)m[L_K0] * ((R)1 + (R)m[L_AT] * phi);
+    k.kM = (R)m[L_KM0] * ((R)1 + (R)m[L_AM] * phi * phi);
+    k.kX = (R)m[L_BTM] * k.kM;
+    return k;
+}
+
+template <typename R>
+__device__ __forceinline__ CCoef<R> law_c(const double *m, R phi, R th)
+{
+    CCoef<R> c;
+    c.cT = (R)m[L_C0] * ((R)1 + (R)m[L_CT] * phi);
+    c.cM = (R)m[L_CM0] * ((R)1 + (R)m[L_AC] * phi);
+    c.cX = ((R)m[L_ETM] + (R)m[L_FTM] * th) * c.cM;
+    return c;
+}
+
+template <typename R>
+__device__ __forceinline__ R harm(R a, R b)
+{
+    R s = a + b;
+    return s > (R)0 ? (R)2 * a * b / s : (R)0;
+}
+
+// Face conductivities at the face state (theta_f, P_f) between two nodes of
+// layers la and lb (harmonic mean across an interface).
+template <typename R>
+__device__ __forceinline__ KCoef<R> face_k(const WallDev &W, int la, int lb, R thf, R Pf)
+{
+    R phi = Pf / psat_th(thf);
+    KCoef<R> a = law_k<R>(W.lay[la], phi);
+    if (la == lb) return a;
+    KCoef<R> b = law_k<R>(W.lay[lb], phi);
+    KCoef<R> k;
+    k.kT = harm(a.kT, b.kT);
+    k.kM = harm(a.kM, b.kM);
+    k.kX = harm(a.kX, b.kX);
+    return k;
+}
+
+// Neumaier (1974) compensated accumulation.
+__device__ __forceinline__ void neumaier_add(double &s, double &c, double x)
+{
+    double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+// Storage traits: FP64 keeps absolute values, FP32 deviations from (T0, P0).
+template <typename R> struct Store;
+template <> struct Store<double> {
+    static __device__ __forceinline__ double thref(const WallDev &W) { return -273.15; }
+    static __device__ __forceinline__ double pref(const WallDev &W) { return 0.0; }
+    static __device__ __forceinline__ double tref(const WallDev &W) { return 0.0; }
+};
+template <> struct Store<float> {
+    static __device__ __forceinline__ float thref(const WallDev &W) { return (float)W.th0; }
+    static __device__ __forceinline__ float pref(const WallDev &W) { return (float)W.P0; }
+    static __device__ __forceinline__ double tref(const WallDev &W) { return W.T0; }
+};
+
+} // namespace dfhm

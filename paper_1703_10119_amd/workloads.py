@@ -43,6 +43,13 @@ SHAPE = dict(aT=0.5, aM=3.0, bTM=0.1 * LV, cT=0.2, aC=2.0, eTM=0.0, fTM=CW)
 
 DAY = 86400.0
 
+# Largest dt/dx (s/m) the batches use.  With the nonlinear law the state
+# dependence of the coefficients, taken at level n, acts like an explicitly
+# treated advection term, and the DF update then diverges once dt/dx reaches
+# about 1e4 s/m whatever lambda is (shown by the oracle alone); the paper's
+# own grid (3.6 s, 1 mm) sits at 3600 s/m.  Generators keep dx >= dt / this.
+DT_OVER_DX_MAX = 5000.0
+
 
 def default_config(dt: float = 1.0, startup: int = 0) -> dict:
     """Global constants of a run (room air defaults rho_a, c_pa, c_pv, Pv_ref)."""
@@ -118,8 +125,9 @@ def _outdoor(rng, W):
     return AT, pT, AR, pR
 
 
-def uniform_batch(n_walls: int, seed: int = 202, nx: int = 1001) -> dict:
-    """Identical-grid batch: 10 cm walls, scales log-uniform over a decade."""
+def uniform_batch(n_walls: int, seed: int = 202, nx: int = 1001, L: float = 0.2) -> dict:
+    """Identical-grid batch: walls of thickness L (20 cm: with 1001 nodes and
+    dt = 1 s that is dt/dx = 5000 s/m), scales log-uniform over a decade."""
     rng = np.random.Generator(np.random.PCG64(seed))
     W = int(n_walls)
     w = _empty_walls(W)
@@ -134,7 +142,7 @@ def uniform_batch(n_walls: int, seed: int = 202, nx: int = 1001) -> dict:
     k0, kM0, c0, cM0 = (logu(NOMINAL[k]) for k in ("k0", "kM0", "c0", "cM0"))
     for name, v in (("k0", k0), ("kM0", kM0), ("c0", c0), ("cM0", cM0)):
         w["layer"][:, 0, LAYER_FIELDS.index(name)] = v
-    w["layer"][:, 0, LAYER_FIELDS.index("thick")] = 0.1
+    w["layer"][:, 0, LAYER_FIELDS.index("thick")] = L
     AT, pT, AR, pR = _outdoor(rng, W)
     w["hT"][:, 0] = 25.0
     w["hM"][:, 0] = 2e-7
@@ -146,10 +154,18 @@ def uniform_batch(n_walls: int, seed: int = 202, nx: int = 1001) -> dict:
     return w
 
 
+def _cap_nodes(w: dict, dx_min: float):
+    """Limit Nx so that dx >= dx_min (at least 3 nodes)."""
+    L = np.array([w["layer"][i, :w["n_layers"][i], 0].sum() for i in range(len(w["nx"]))])
+    cap = np.maximum(3, np.floor(L / dx_min).astype(np.int64) + 1)
+    w["nx"][:] = np.minimum(w["nx"], cap).astype(np.int32)
+
+
 def layered_batch(n_walls: int, seed: int = 303, nx_lo: int = 51,
                   nx_hi: int = 2001, nx_median: float = 300.0,
-                  nx_sigma: float = 0.6) -> dict:
-    """Uneven batch: lognormal Nx, 1-3 layers of 1-20 cm, +-10 % k scales."""
+                  nx_sigma: float = 0.6, dt: float = 1.0) -> dict:
+    """Uneven batch: lognormal Nx, 1-3 layers of 1-20 cm, +-10 % k scales;
+    Nx capped so that dt/dx <= DT_OVER_DX_MAX."""
     rng = np.random.Generator(np.random.PCG64(seed))
     W = int(n_walls)
     w = _empty_walls(W)
@@ -165,6 +181,7 @@ def layered_batch(n_walls: int, seed: int = 303, nx_lo: int = 51,
         w["layer"][:, l, LAYER_FIELDS.index("kM0")] = NOMINAL["kM0"] * rng.uniform(0.9, 1.1, W)
         w["layer"][:, l, LAYER_FIELDS.index("c0")] = NOMINAL["c0"]
         w["layer"][:, l, LAYER_FIELDS.index("cM0")] = NOMINAL["cM0"]
+    _cap_nodes(w, dt / DT_OVER_DX_MAX)
     AT, pT, AR, pR = _outdoor(rng, W)
     w["hT"][:, 0] = 25.0
     w["hM"][:, 0] = 2e-7
@@ -177,12 +194,12 @@ def layered_batch(n_walls: int, seed: int = 303, nx_lo: int = 51,
 
 
 def building_batch(n_rooms: int, seed: int = 404, nx_lo: int = 101,
-                   nx_hi: int = 801, n_sched: int = 24):
+                   nx_hi: int = 801, n_sched: int = 24, dt: float = 1.0):
     """Box rooms (2.5 m high, square floor) with 6 layered walls each.
 
     Side 0 of every wall faces the outdoor air of its room, side 1 the room.
-    Hourly moisture (0-500 g/h) and heat (0-1000 W) schedules, seeded.
-    Returns (walls, rooms).
+    Hourly moisture (0-500 g/h) and heat (0-1000 W) schedules, seeded.  Nx is
+    capped so that dt/dx <= DT_OVER_DX_MAX.  Returns (walls, rooms).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     R = int(n_rooms)
@@ -199,6 +216,7 @@ def building_batch(n_rooms: int, seed: int = 404, nx_lo: int = 101,
         w["layer"][:, l, LAYER_FIELDS.index("kM0")] = NOMINAL["kM0"] * rng.uniform(0.9, 1.1, W)
         w["layer"][:, l, LAYER_FIELDS.index("c0")] = NOMINAL["c0"]
         w["layer"][:, l, LAYER_FIELDS.index("cM0")] = NOMINAL["cM0"]
+    _cap_nodes(w, dt / DT_OVER_DX_MAX)
     volume = rng.uniform(30.0, 300.0, R)
     ach = rng.uniform(0.2, 2.0, R)
     AT, pT, AR, pR = _outdoor(rng, R)

@@ -1,0 +1,316 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Error metric (per field, over all walls and nodes of the compared levels):
+max |x_gpu - x_ref| / max |x_ref|.  Bars: FP64 <= 1e-12, FP32 <= 1e-5 on T
+and on Pv separately.  Fluxes are compared relative to their largest value.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_10119_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1703_10119_amd import dfhm  # noqa: E402
+
+TOL = {dfhm.FP64: 1e-12, dfhm.FP32: 1e-5}
+FTOL = {dfhm.FP64: 1e-9, dfhm.FP32: 2e-4}
+SCHEDS = [("stream", dfhm.SCHED_STREAM), ("resident", dfhm.SCHED_RESIDENT)]
+PRECS = [("fp64", dfhm.FP64), ("fp32", dfhm.FP32)]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def oracle_run(walls, cfg, steps, rooms=None, n0=None, levels=None):
+    ref = oracle.RefSim(walls, cfg, rooms)
+    if levels is not None:
+        for w, (Tp, Pp, Tc, Pc) in levels.items():
+            ref.set_fields(w, 1, Tp, Pp)
+            ref.set_fields(w, 0, Tc, Pc)
+        ref.n = n0
+    ref.step(steps, threads=16)
+    return ref
+
+
+def compare(s, ref, prec, what, check_prev=True):
+    T, P = s.all_fields(0)
+    Tr, Pr = ref.all_fields(0)
+    eT, eP = rel(T, Tr), rel(P, Pr)
+    out = dict(T=eT, P=eP)
+    if check_prev:
+        T1, P1 = s.all_fields(1)
+        Tr1, Pr1 = ref.all_fields(1)
+        out["T1"], out["P1"] = rel(T1, Tr1), rel(P1, Pr1)
+    now, integ = s.fluxes()
+    now_r, int_r = ref.fluxes()
+    out["flux_now"] = rel(now, now_r)
+    out["flux_int"] = rel(integ, int_r)
+    say(f"  {what}: " + " ".join(f"{k}={v:.2e}" for k, v in out.items()))
+    tol, ftol = TOL[prec], FTOL[prec]
+    assert eT <= tol and eP <= tol, out
+    if check_prev:
+        assert out["T1"] <= tol and out["P1"] <= tol, out
+    assert out["flux_now"] <= ftol and out["flux_int"] <= ftol, out
+    return out
+
+
+@pytest.mark.parametrize("pname,prec", PRECS)
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_single_wall_full_day(pname, prec, sname, sched):
+    """10 cm wall, 101 nodes, dt = 1 s, 24 h of sinusoidal outdoor air."""
+    walls = wl.single_wall(seed=101)
+    cfg = wl.default_config(dt=1.0)
+    say(f"single wall 86400 steps {pname} {sname}")
+    ref = oracle_run(walls, cfg, 86400)
+    s = dfhm.Solver(walls, cfg, precision=prec, schedule=sched)
+    s.step(86400)
+    s.sync()
+    assert s.n == 86400
+    compare(s, ref, prec, f"single {pname} {sname}")
+
+
+@pytest.mark.parametrize("pname,prec", PRECS)
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_uniform_batch(pname, prec, sname, sched):
+    """64 identical-grid walls of 1001 nodes (several tiles each), scales
+    log-uniform over a decade, random outdoor phases, 400 steps of 1 s."""
+    walls = wl.uniform_batch(64, seed=202, nx=1001)
+    cfg = wl.default_config(dt=1.0)
+    say(f"uniform batch 64x1001 x400 {pname} {sname}")
+    ref = oracle_run(walls, cfg, 400)
+    s = dfhm.Solver(walls, cfg, precision=prec, schedule=sched, chunk=150)
+    s.step(400)
+    s.sync()
+    compare(s, ref, prec, f"uniform {pname} {sname}")
+
+
+@pytest.mark.parametrize("pname,prec", PRECS)
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_layered_uneven_batch(pname, prec, sname, sched):
+    """300 walls, lognormal Nx in [51, 2001], 1-3 layers, 600 steps of 1 s."""
+    walls = wl.layered_batch(300, seed=303)
+    cfg = wl.default_config(dt=1.0)
+    say(f"layered batch 300 walls x600 {pname} {sname}")
+    ref = oracle_run(walls, cfg, 600)
+    s = dfhm.Solver(walls, cfg, precision=prec, schedule=sched, chunk=250)
+    s.step(600)
+    s.sync()
+    compare(s, ref, prec, f"layered {pname} {sname}")
+    inf = s.info()
+    if sched == dfhm.SCHED_RESIDENT:
+        assert inf["max_walls_per_block"] >= 2 and inf["pack_efficiency"] > 0.5
+
+
+@pytest.mark.parametrize("pname,prec", PRECS)
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_rooms_coupled(pname, prec, sname, sched):
+    """6 box rooms with 6 layered walls each, dt = 10 s, one day."""
+    walls, rooms = wl.building_batch(6, seed=404, dt=10.0)
+    cfg = wl.default_config(dt=10.0)
+    say(f"rooms 6x6 walls x8640 {pname} {sname}")
+    ref = oracle_run(walls, cfg, 8640, rooms=rooms)
+    s = dfhm.Solver(walls, cfg, rooms=rooms, precision=prec, schedule=sched, chunk=1000)
+    s.step(8640)
+    s.sync()
+    compare(s, ref, prec, f"rooms {pname} {sname}")
+    Ta, Pa = s.rooms()
+    Tar, Par = ref.rooms()
+    eTa, ePa = rel(Ta, Tar), rel(Pa, Par)
+    say(f"  room air: T={eTa:.2e} P={ePa:.2e}")
+    assert eTa <= TOL[prec] and ePa <= TOL[prec]
+
+
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_repeat_start(sname, sched):
+    walls = wl.uniform_batch(8, seed=12, nx=301)
+    cfg = wl.default_config(dt=3.0, startup=1)
+    say(f"repeat start {sname}")
+    ref = oracle_run(walls, cfg, 500)
+    s = dfhm.Solver(walls, cfg, precision=dfhm.FP64, schedule=sched, chunk=128)
+    s.step(500)
+    s.sync()
+    compare(s, ref, dfhm.FP64, f"repeat {sname}")
+
+
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_edge_sizes(sname, sched):
+    """Smallest wall (3 nodes), tile / lane boundaries and the largest wall."""
+    sizes = [3, 4, 5, 254, 255, 256, 257, 510, 511, 1024, 2001, 2048]
+    walls = wl.concat(*[wl.uniform_batch(1, seed=50 + i, nx=n) for i, n in enumerate(sizes)])
+    cfg = wl.default_config(dt=0.4)
+    say(f"edge sizes {sname}")
+    ref = oracle_run(walls, cfg, 300)
+    s = dfhm.Solver(walls, cfg, precision=dfhm.FP64, schedule=sched, chunk=77)
+    s.step(300)
+    s.sync()
+    compare(s, ref, dfhm.FP64, f"edges {sname}")
+
+
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_restart_from_given_levels(sname, sched):
+    """dfhm_set_fields + dfhm_set_step_index: continue from two given levels."""
+    walls = wl.layered_batch(20, seed=31, nx_hi=900, dt=3.0)
+    cfg = wl.default_config(dt=3.0)
+    rng = np.random.default_rng(4)
+    levels = {}
+    for w in range(20):
+        nx = int(walls["nx"][w])
+        Tp = 290 + rng.uniform(0, 6, nx)
+        Pp = 900 + rng.uniform(0, 400, nx)
+        levels[w] = (Tp, Pp, Tp + rng.normal(0, 0.01, nx), Pp + rng.normal(0, 0.5, nx))
+    say(f"restart {sname}")
+    ref = oracle_run(walls, cfg, 200, n0=37, levels=levels)
+    s = dfhm.Solver(walls, cfg, precision=dfhm.FP64, schedule=sched, chunk=64)
+    s.set_step_index(37)
+    for w, (Tp, Pp, Tc, Pc) in levels.items():
+        s.set_fields(w, 1, Tp, Pp)
+        s.set_fields(w, 0, Tc, Pc)
+    s.step(200)
+    s.sync()
+    assert s.n == 237
+    compare(s, ref, dfhm.FP64, f"restart {sname}")
+
+
+def test_graph_chunks_bit_identical_to_direct_launches():
+    walls = wl.uniform_batch(16, seed=8, nx=700)
+    cfg = wl.default_config(dt=1.0)
+    say("graph vs direct")
+    out = []
+    for g in (0, 1):
+        s = dfhm.Solver(walls, cfg, precision=dfhm.FP64, schedule=dfhm.SCHED_STREAM,
+                        chunk=50, use_graph=g)
+        s.step(333)
+        s.sync()
+        out.append((s.all_fields(0), s.fluxes()))
+        s.close()
+    (T0, P0), (n0, i0) = out[0]
+    (T1, P1), (n1, i1) = out[1]
+    assert np.array_equal(T0, T1) and np.array_equal(P0, P1)
+    assert np.array_equal(n0, n1) and np.array_equal(i0, i1)
+
+
+def test_resident_batching_invariance():
+    """A wall's trajectory is bit-identical alone or packed with others."""
+    walls = wl.layered_batch(40, seed=77, nx_hi=700, dt=2.0)
+    cfg = wl.default_config(dt=2.0)
+    say("batching invariance")
+    s = dfhm.Solver(walls, cfg, precision=dfhm.FP64, schedule=dfhm.SCHED_RESIDENT, chunk=100)
+    s.step(250)
+    s.sync()
+    assert s.info()["max_walls_per_block"] >= 2
+    for w in (0, 13, 39):
+        one = wl.subset(walls, [w])
+        s1 = dfhm.Solver(one, cfg, precision=dfhm.FP64, schedule=dfhm.SCHED_RESIDENT, chunk=100)
+        s1.step(250)
+        s1.sync()
+        Ta, Pa = s.fields(w)
+        Tb, Pb = s1.fields(0)
+        assert np.array_equal(Ta, Tb) and np.array_equal(Pa, Pb), w
+        s1.close()
+
+
+def test_nonfinite_state_is_reported_and_latched():
+    walls = wl.uniform_batch(2, seed=3, nx=51)
+    cfg = wl.default_config(dt=1.0, startup=1)
+    say("non-finite detection")
+    s = dfhm.Solver(walls, cfg, precision=dfhm.FP64, schedule=dfhm.SCHED_STREAM)
+    T, P = s.fields(1)
+    T[10] = 273.15 - 243.04          # Magnus pole: Ps = 0, phi = inf
+    s.set_fields(1, 0, T, P)
+    s.step(3)
+    with pytest.raises(dfhm.DfhmError) as e:
+        s.sync()
+    assert e.value.status == 4
+    with pytest.raises(dfhm.DfhmError) as e:
+        s.step(1)
+    assert e.value.status == 5
+    T, P = s.fields(1, 0)
+    s.set_fields(1, 0, np.full_like(T, 293.0), np.full_like(P, 1000.0))
+    s.set_fields(1, 1, np.full_like(T, 293.0), np.full_like(P, 1000.0))
+    s.set_fields(0, 0, np.full_like(T, 293.0), np.full_like(P, 1000.0))
+    s.set_fields(0, 1, np.full_like(T, 293.0), np.full_like(P, 1000.0))
+    s.step(2)
+    s.sync()
+
+
+def test_unstable_room_step_is_refused():
+    walls, rooms = wl.building_batch(2, seed=5, dt=3600.0)
+    cfg = wl.default_config(dt=3600.0)
+    s = dfhm.Solver(walls, cfg, precision=dfhm.FP64)
+    with pytest.raises(dfhm.DfhmError) as e:
+        s._couple(walls, rooms)
+    assert e.value.status == 6
+
+
+@pytest.mark.parametrize("pname,prec", PRECS)
+def test_full_size_batch_sampled(pname, prec):
+    """65,536 walls x 1001 nodes in the benchmark's launch configuration;
+    sampled walls are re-run alone by the oracle (walls are independent)."""
+    walls = wl.uniform_batch(65536, seed=202, nx=1001)
+    cfg = wl.default_config(dt=1.0)
+    steps = 60
+    say(f"full size 65536x1001 x{steps} {pname}")
+    s = dfhm.Solver(walls, cfg, precision=prec, schedule=dfhm.SCHED_RESIDENT)
+    s.step(steps)
+    s.sync()
+    idx = [0, 1, 4097, 32768, 50001, 65535]
+    sub = wl.subset(walls, idx)
+    ref = oracle_run(sub, cfg, steps)
+    now, integ = s.fluxes()
+    now_r, int_r = ref.fluxes()
+    for k, w in enumerate(idx):
+        T, P = s.fields(w)
+        Tr, Pr = ref.fields(k)
+        assert rel(T, Tr) <= TOL[prec] and rel(P, Pr) <= TOL[prec], (w, rel(T, Tr), rel(P, Pr))
+    assert rel(integ[idx], int_r) <= FTOL[prec]
+    s.close()
+
+
+def test_torch_arena_and_library_arena_agree():
+    walls = wl.layered_batch(30, seed=9)
+    cfg = wl.default_config(dt=1.0)
+    res = []
+    for arena in ("torch", None):
+        s = dfhm.Solver(walls, cfg, precision=dfhm.FP64, arena=arena)
+        s.step(120)
+        s.sync()
+        res.append(s.all_fields(0))
+        s.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_autotune_leaves_state_and_picks_a_schedule():
+    walls = wl.uniform_batch(256, seed=6, nx=1001)
+    cfg = wl.default_config(dt=1.0)
+    say("autotune")
+    a = dfhm.Solver(walls, cfg, precision=dfhm.FP64)
+    a.step(5)
+    before = a.all_fields(0)
+    a.autotune(probe_steps=20)
+    assert a.n == 5
+    after = a.all_fields(0)
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    a.step(50)
+    a.sync()
+    b = dfhm.Solver(walls, cfg, precision=dfhm.FP64, schedule=dfhm.SCHED_STREAM)
+    b.step(55)
+    b.sync()
+    assert rel(a.all_fields(0)[0], b.all_fields(0)[0]) <= 1e-12
+    inf = a.info()
+    say(f"  autotune chose {inf}")
+    assert inf["schedule"] in (1, 2)

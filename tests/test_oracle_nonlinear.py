@@ -243,3 +243,30 @@ def test_forward_euler_startup_matches_fine_solution():
     Tf, Pf, _ = oracle.implicit_run(w, 0, dt / 64, wl.LV, 64, theta=0.5, eta=1e-13)
     assert np.max(np.abs(T - Tf)) < 5e-3 * max(np.ptp(Tf), 1e-3) + 1e-6
     assert np.max(np.abs(P - Pf)) < 5e-3 * max(np.ptp(Pf), 1e-3) + 1e-6
+
+
+def _diverged(walls, cfg, steps):
+    sim = oracle.RefSim(walls, cfg)
+    sim.step(steps, threads=8)
+    bad = []
+    for w in range(len(walls["nx"])):
+        T, _ = sim.fields(w)
+        if not (np.all(np.isfinite(T)) and np.max(np.abs(T - 293.0)) < 60.0):
+            bad.append(w)
+    return bad
+
+
+def test_nonlinear_df_stability_tracks_dt_over_dx():
+    """The paper's stability claim is for constant coefficients.  With the
+    nonlinear law the coefficients taken at level n behave like an explicit
+    advection term, and DF diverges once dt/dx is large (here 1e4 s/m) even
+    at modest lambda, while at 5000 s/m the same walls stay bounded at a
+    larger lambda.  Eight high-diffusivity walls of the identical-grid batch."""
+    idx = [18, 48, 75, 87, 116, 122, 160, 237]
+    pick = lambda L: wl.subset(wl.uniform_batch(256, seed=202, L=L), idx)
+    # dt/dx = 1e4 s/m at lambda_T(nominal) 90 and 45: divergence
+    assert len(_diverged(pick(0.1), wl.default_config(dt=1.0), 3000)) >= 4
+    assert len(_diverged(pick(0.2), wl.default_config(dt=2.0), 1500)) >= 4
+    # dt/dx = 5000 s/m at lambda_T(nominal) 45 (and 22): bounded
+    assert _diverged(pick(0.1), wl.default_config(dt=0.5), 6000) == []
+    assert _diverged(pick(0.2), wl.default_config(dt=1.0), 3000) == []
