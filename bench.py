@@ -1,0 +1,160 @@
+"""Benchmark: Dufort-Frankel cell-updates/s on one MI355X.
+
+Workload: 65,536 identical-grid walls (1001 nodes, 30 cm), per-wall material
+scales log-uniform over a decade, random outdoor sinusoids, dt = 1 s (the
+batched identical-grid configuration).  A step is one DF time step of the
+whole batch (outdoor air, coefficients, moisture and heat updates, surface
+fluxes and their compensated integrals).  Inputs are resident in HBM before
+the timed region; the start-up step runs in the warm-up.
+
+Prints one JSON line (value = FP64 cell-updates/s; the FP32 run of the same
+batch is reported under "fp32").
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+N_WALLS = 65536
+NX = 1001
+DT = 1.0
+# Algorithmic floating-point operations per cell-update of the DF step (one
+# node, both fields): face coefficients at the face state 21, node
+# coefficients 17, moisture update 9, heat update 22 -- 69 operations, of
+# which 2 exponentials and 4 divisions, each counted as one operation (FMA as
+# two).  The per-wall outdoor air and flux work adds < 1 % at 1001 nodes.
+FLOPS_PER_CELL = 69
+# Minimum HBM bytes per cell-update of a streaming step: read T, P at n-1 and
+# n, write T, P at n+1 (8 B each in FP64, 4 B in FP32).
+BYTES_PER_CELL = {"f64": 48, "f32": 24}
+PEAK = {"f64": 78.6, "f32": 157.3}       # TFLOP/s, MI355X vector
+HBM_PEAK = 8000.0                         # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--schedule", default="resident", choices=["auto", "stream", "resident"])
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--walls", type=int, default=N_WALLS)
+    ap.add_argument("--cpu-walls", type=int, default=1024)
+    ap.add_argument("--cpu-steps", type=int, default=1000)
+    return ap.parse_args()
+
+
+def run_gpu(dfhm, walls, cfg, prec, schedule, steps, warmup):
+    import torch
+    sched = {"auto": dfhm.SCHED_AUTO, "stream": dfhm.SCHED_STREAM,
+             "resident": dfhm.SCHED_RESIDENT}[schedule]
+    s = dfhm.Solver(walls, cfg, precision=prec, schedule=sched)
+    if schedule == "auto":
+        s.autotune(probe_steps=50)
+    s.step(warmup)
+    s.sync()
+    info = s.info()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s.sync()
+    ms = e0.elapsed_time(e1)
+    now, integ = s.fluxes()
+    finite = bool(np.all(np.isfinite(integ)))
+    s.close()
+    return ms, info, finite
+
+
+def roofline(dtype, cells, steps, ms, info):
+    if info["schedule"] == 2:   # resident: VALU-bound, one launch per chunk
+        launches = math.ceil(steps / info["chunk_steps"])
+        per_launch_s = ms / 1e3 / launches
+        flops = FLOPS_PER_CELL * cells * steps / launches
+        ach = flops / per_launch_s / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK[dtype],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK[dtype], 4), "traffic": None,
+                "kernel": "k_df_resident", "launch_ms": round(per_launch_s * 1e3, 3)}
+    per_launch_s = ms / 1e3 / steps
+    ach = BYTES_PER_CELL[dtype] * cells / per_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK, 4), "traffic": None, "kernel": "k_df_stream",
+            "launch_ms": round(per_launch_s * 1e3, 4)}
+
+
+def cpu_baseline(walls_fn, cfg, n_walls, steps):
+    import oracle
+    oracle.build()
+    walls = walls_fn(n_walls)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sim = oracle.RefSim(walls, cfg)
+    sim.step(1, threads=threads)          # start-up step outside the timing
+    t = time.perf_counter()
+    sim.step(steps, threads=threads)
+    dt = time.perf_counter() - t
+    cells = int(np.sum(walls["nx"])) * steps
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_walls} walls x {NX} nodes x {steps} steps of the same batch "
+                      f"(FP64 C oracle, OpenMP over walls), {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the batch shards by "
+              "walls with no per-step communication, see the design notes", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1703_10119_amd import dfhm, workloads as wl
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = wl.default_config(dt=DT)
+    walls = wl.uniform_batch(a.walls, seed=202, nx=NX)
+    cells = a.walls * NX
+    ms64, info64, fin64 = run_gpu(dfhm, walls, cfg, dfhm.FP64, a.schedule, a.steps, a.warmup)
+    value = cells * a.steps / (ms64 / 1e3)
+    out = {
+        "metric": "DF cell-updates/s (fp64 vs fp32 batched) + surrogate speedup at <=1% flux err",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms64 / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "identical-grid batch: 65,536 walls x 1001 nodes (30 cm), "
+                               "dt = 1 s, log-uniform scales, random outdoor sinusoids",
+                   "walls": a.walls, "nx": NX, "dt_s": DT,
+                   "schedule": ["", "stream", "resident"][info64["schedule"]],
+                   "block_threads": info64["block_threads"],
+                   "nodes_per_thread": info64["nodes_per_thread"],
+                   "chunk_steps": info64["chunk_steps"]},
+        "roofline": roofline("f64", cells, a.steps, ms64, info64),
+        "finite": fin64,
+    }
+    if not a.no_fp32:
+        ms32, info32, fin32 = run_gpu(dfhm, walls, cfg, dfhm.FP32, a.schedule, a.steps, a.warmup)
+        out["fp32"] = {"value": cells * a.steps / (ms32 / 1e3), "ms_per_step": ms32 / a.steps,
+                       "dtype": "f32", "roofline": roofline("f32", cells, a.steps, ms32, info32),
+                       "finite": fin32}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(
+            lambda n: wl.uniform_batch(N_WALLS, seed=202, nx=NX) if n == N_WALLS
+            else wl.subset(wl.uniform_batch(N_WALLS, seed=202, nx=NX), np.arange(n)),
+            cfg, a.cpu_walls, a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -287,9 +287,22 @@ dfhm_status step_stream(dfhm_ctx *c, int64_t nsteps)
             if (!c->graph_exec || c->graph_steps != chunk) {
                 if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
                 if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
-                HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                enqueue_stream_chunk<R>(c, chunk);
-                HIP_TRY(c, hipStreamEndCapture(c->stream, &c->graph));
+                // capture on a private stream (the caller's may be the legacy
+                // default stream, which cannot be captured); replay on theirs
+                hipStream_t cap = nullptr;
+                HIP_TRY(c, hipStreamSynchronize(c->stream));
+                HIP_TRY(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+                hipStream_t user = c->stream;
+                c->stream = cap;
+                hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    enqueue_stream_chunk<R>(c, chunk);
+                    e = hipStreamEndCapture(cap, &c->graph);
+                }
+                c->stream = user;
+                (void)hipStreamDestroy(cap);
+                if (e != hipSuccess)
+                    return fail(c, DFHM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
                 HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
                 c->graph_steps = chunk;
             }
