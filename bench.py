@@ -51,7 +51,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--walls", type=int, default=N_WALLS)
     ap.add_argument("--cpu-walls", type=int, default=1024)
-    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--cpu-steps", type=int, default=10000)
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied by a plain device copy before the run (counter calibration)")
     return ap.parse_args()
 
 
@@ -123,9 +126,21 @@ def main():
     from paper_1703_10119_amd import dfhm, workloads as wl
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = wl.default_config(dt=DT)
     walls = wl.uniform_batch(a.walls, seed=202, nx=NX)
     cells = a.walls * NX
+    if a.precision == "fp32":
+        ms32, info32, fin32 = run_gpu(dfhm, walls, cfg, dfhm.FP32, a.schedule, a.steps, a.warmup)
+        print(json.dumps({"fp32_value": cells * a.steps / (ms32 / 1e3),
+                          "roofline": roofline("f32", cells, a.steps, ms32, info32)}), flush=True)
+        return
     ms64, info64, fin64 = run_gpu(dfhm, walls, cfg, dfhm.FP64, a.schedule, a.steps, a.warmup)
     value = cells * a.steps / (ms64 / 1e3)
     out = {
@@ -143,7 +158,7 @@ def main():
         "roofline": roofline("f64", cells, a.steps, ms64, info64),
         "finite": fin64,
     }
-    if not a.no_fp32:
+    if not a.no_fp32 and a.precision == "both":
         ms32, info32, fin32 = run_gpu(dfhm, walls, cfg, dfhm.FP32, a.schedule, a.steps, a.warmup)
         out["fp32"] = {"value": cells * a.steps / (ms32 / 1e3), "ms_per_step": ms32 / a.steps,
                        "dtype": "f32", "roofline": roofline("f32", cells, a.steps, ms32, info32),

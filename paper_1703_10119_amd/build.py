@@ -12,6 +12,9 @@ LIB = os.path.join(HERE, "libdfhm.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no implicit contraction: every fused multiply-add is written out, so a
+    # node's arithmetic does not depend on where it sits in a workgroup
+    "-ffp-contract=off",
     # packed FP32 instructions stay off (never hand-written, never generated)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),

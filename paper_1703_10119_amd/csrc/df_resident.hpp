@@ -52,18 +52,6 @@ struct Shape {
 template <typename R>
 constexpr size_t res_dyn_lds(int nt) { return sizeof(R) * 14 * (size_t)nt; }
 
-template <typename R>
-__device__ __forceinline__ R magnus_exp_neg(R th)
-{
-    // exp(-17.625 theta / (theta + 243.04)); phi = P exp(-a) / 610.94
-    return exp(-(R)17.625 * th / (th + (R)243.04));
-}
-template <>
-__device__ __forceinline__ float magnus_exp_neg<float>(float th)
-{
-    return __expf(-17.625f * th / (th + 243.04f));
-}
-
 template <typename R, int NPT, int NT>
 __global__ void __launch_bounds__(NT)
 k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ block_walls,
@@ -74,14 +62,19 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
               double *__restrict__ flux, int *__restrict__ bad,
               const int64_t *__restrict__ step_base, int ksteps, RunConst rc, Shape sh)
 {
+    static_assert(NT >= 2 * kResMaxWalls, "one lane per wall side computes the ambient");
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int32_t s_wstart[kResMaxWalls + 1];
     __shared__ int32_t s_wid[kResMaxWalls];
     __shared__ int32_t s_wroom[kResMaxWalls];           // local zone or -1
     __shared__ double s_flux[kResMaxWalls][12];
     __shared__ double s_surf[2][kResMaxWalls][2][2];   // [par][slot][side][T,P] level n
+    __shared__ double s_amb[2][kResMaxWalls][2][2];    // [par][slot][side][T,P] ambient at t^n
     __shared__ double s_room[2][kResMaxRooms][2];      // [par][zone][T,P]
     __shared__ int32_t s_rid[kResMaxRooms];
+    // outdoor sinusoids per wall side: T mean, T amp, RH mean, RH amp,
+    // sin/cos of the T and RH phases at t^n, sin/cos of the per-step increments
+    __shared__ double s_rot[kResMaxWalls][2][12];
 
     constexpr int nthreads = NT;
     const int t = threadIdx.x;
@@ -123,6 +116,22 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         s_wroom[t] = lr;
     }
 
+    // ---- ambient lanes: one per wall side; the outdoor sinusoids advance by
+    // an exact rotation through the chunk, anchored at t^n0 (state in LDS)
+    const bool amb_lane = t < 2 * nwb;
+    const int amb_slot = t >> 1, amb_side = t & 1;
+    if (amb_lane) {
+        const WallDev &W = walls[block_walls[B.w_begin + amb_slot]];
+        const double *ST = W.Tamb[amb_side], *SR = W.RHamb[amb_side];
+        const double t0 = (double)n0 * rc.dt;
+        double *st = s_rot[amb_slot][amb_side];
+        st[0] = ST[0]; st[1] = ST[1]; st[2] = SR[0]; st[3] = SR[1];
+        sincos(2.0 * dpi() * t0 / ST[2] + ST[3], &st[4], &st[5]);
+        sincos(2.0 * dpi() * t0 / SR[2] + SR[3], &st[6], &st[7]);
+        sincos(2.0 * dpi() * rc.dt / ST[2], &st[8], &st[9]);
+        sincos(2.0 * dpi() * rc.dt / SR[2], &st[10], &st[11]);
+    }
+
     // ---- per-node set-up: levels, scales, flags
     const int cb = (int)(n0 & 1);
     const R *Tc = cb ? T1b : T0b;
@@ -143,35 +152,35 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             kf0[q] = kMf0[q] = 0;
             info[q] = 0;
             if (b < B.n_nodes) {
-            while (b >= s_wstart[slot + 1]) ++slot;
-            const WallDev &W = walls[s_wid[slot]];
-            const int j = b - s_wstart[slot];
-            const int64_t g = (int64_t)W.off + j;
-            Tm[q] = Tp[g]; Pm[q] = Pp[g];
-            Tn[q] = Tc[g]; Pn[q] = Pc[g];
-            const int la = lay[g];
-            const double rinv = 1.0 / W.r;
-            c0s[q] = (R)(W.lay[la][L_C0] * rinv);
-            cM0s[q] = (R)(W.lay[la][L_CM0] * rinv);
-            if (j < W.nx - 1) {
-                const int lb = lay[g + 1];
-                double a = W.lay[la][L_K0], bb = W.lay[lb][L_K0];
-                double am = W.lay[la][L_KM0], bm = W.lay[lb][L_KM0];
-                if (la != lb) {
-                    double s1 = a + bb, s2 = am + bm;
-                    a = s1 > 0.0 ? 2.0 * a * bb / s1 : 0.0;
-                    am = s2 > 0.0 ? 2.0 * am * bm / s2 : 0.0;
+                while (b >= s_wstart[slot + 1]) ++slot;
+                const WallDev &W = walls[s_wid[slot]];
+                const int j = b - s_wstart[slot];
+                const int64_t g = (int64_t)W.off + j;
+                Tm[q] = Tp[g]; Pm[q] = Pp[g];
+                Tn[q] = Tc[g]; Pn[q] = Pc[g];
+                const int la = lay[g];
+                const double rinv = 1.0 / W.r;
+                c0s[q] = (R)(W.lay[la][L_C0] * rinv);
+                cM0s[q] = (R)(W.lay[la][L_CM0] * rinv);
+                if (j < W.nx - 1) {
+                    const int lb = lay[g + 1];
+                    double a = W.lay[la][L_K0], bb = W.lay[lb][L_K0];
+                    double am = W.lay[la][L_KM0], bm = W.lay[lb][L_KM0];
+                    if (la != lb) {
+                        double s1 = a + bb, s2 = am + bm;
+                        a = s1 > 0.0 ? 2.0 * a * bb / s1 : 0.0;
+                        am = s2 > 0.0 ? 2.0 * am * bm / s2 : 0.0;
+                    }
+                    kf0[q] = (R)a;
+                    kMf0[q] = (R)am;
                 }
-                kf0[q] = (R)a;
-                kMf0[q] = (R)am;
-            }
-            info[q] = slot | ((j == 0) << 8) | ((j == W.nx - 1) << 9) | (1 << 10);
+                info[q] = slot | ((j == 0) << 8) | ((j == W.nx - 1) << 9) | (1 << 10);
             }
         }
     }
-    // nodes of one lane may lie in different walls: per-node references
     const R aT = (R)sh.aT, aM = (R)sh.aM, bTM = (R)sh.bTM, cT = (R)sh.cT, aC = (R)sh.aC,
             eTM = (R)sh.eTM, fTM = (R)sh.fTM;
+    // nodes of one lane may lie in different walls: per-node references
     R thref[NPT], pref[NPT];
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
@@ -179,6 +188,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         thref[q] = Store<R>::thref(W);
         pref[q] = Store<R>::pref(W);
     }
+    const R ps_inv = (R)(1.0 / 610.94);
     __syncthreads();
 
     for (int i = 0; i < ksteps; ++i) {
@@ -186,7 +196,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         // and the swap at its end restores the roles
         const int64_t n = n0 + i;
         const int par = (int)(n & 1);
-        // ---- A: publish halos and surface values
+        // ---- A: publish halos, surface values and the ambient at t^n
         R *hp = halo + par * 4 * nthreads;
         hp[t] = Tn[0];
         hp[nthreads + t] = Pn[0];
@@ -198,15 +208,34 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const int f = info[q];
                 if (f & (3 << 8)) {
                     const int s = f & 0xff;
-                    const WallDev &W = walls[s_wid[s]];
                     const int side = (f >> 8) & 1 ? 0 : 1;
-                    s_surf[par][s][side][0] = Store<R>::tref(W) + (double)Tn[q];
+                    s_surf[par][s][side][0] = Store<R>::tref(walls[s_wid[s]]) + (double)Tn[q];
                     s_surf[par][s][side][1] = (double)pref[q] + (double)Pn[q];
                 }
             }
         }
+        if (amb_lane) {
+            const WallDev &W = walls[s_wid[amb_slot]];
+            double Ta, Pa;
+            double *st = s_rot[amb_slot][amb_side];
+            if (W.room >= 0 && W.room_side == amb_side) {
+                const int z = s_wroom[amb_slot];
+                Ta = s_room[par][z][0];
+                Pa = s_room[par][z][1];
+            } else {
+                Ta = st[0] + st[1] * st[4];
+                Pa = (st[2] + st[3] * st[6]) * psat_th(Ta - 273.15);
+            }
+            s_amb[par][amb_slot][amb_side][0] = Ta;
+            s_amb[par][amb_slot][amb_side][1] = Pa;
+            const double sT = st[4], cT = st[5], sR = st[6], cR = st[7];
+            st[4] = fma(sT, st[9], cT * st[8]);
+            st[5] = fma(cT, st[9], -sT * st[8]);
+            st[6] = fma(sR, st[11], cR * st[10]);
+            st[7] = fma(cR, st[11], -sR * st[10]);
+        }
         __syncthreads();
-        // ---- B: faces, zones
+        // ---- B: faces and node humidity ratios, zones
         const R Tr_nb = t + 1 < nthreads ? hp[t + 1] : (R)0;
         const R Pr_nb = t + 1 < nthreads ? hp[nthreads + t + 1] : (R)0;
         const R Tl_nb = t > 0 ? hp[2 * nthreads + t - 1] : (R)0;
@@ -235,19 +264,35 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             s_room[par ^ 1][t][1] = Pa + rc.dt * G / (mass / rc.Pv_ref);
             s_room[par ^ 1][t][0] = Ta + rc.dt * Q / (mass * cma);
         }
-        R kT[NPT], kM[NPT], kX[NPT];
+        R kT[NPT], kM[NPT], kX[NPT], phn[NPT];
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
             const R Tr = q + 1 < NPT ? Tn[q + 1 < NPT ? q + 1 : q] : Tr_nb;
             const R Pr = q + 1 < NPT ? Pn[q + 1 < NPT ? q + 1 : q] : Pr_nb;
-            const R thf = thref[q] + (R)0.5 * (Tn[q] + Tr);
-            const R Pf = pref[q] + (R)0.5 * (Pn[q] + Pr);
-            const R phi = Pf * magnus_exp_neg<R>(thf) * (R)(1.0 / 610.94);
             // a node without a right face (wall end, padding) has zero scales;
-            // the select keeps a non-physical face state from leaking a NaN
+            // its face state is its own, so that nothing from the next wall or
+            // from padding enters its arithmetic (and no NaN can leak in)
             const bool live = kf0[q] != (R)0 || kMf0[q] != (R)0;
-            kT[q] = live ? kf0[q] * ((R)1 + aT * phi) : (R)0;
-            kM[q] = live ? kMf0[q] * ((R)1 + aM * phi * phi) : (R)0;
+            const R thn = thref[q] + Tn[q];
+            const R thf = live ? fma((R)0.5, Tn[q] + Tr, thref[q]) : thn;
+            const R Pf = live ? fma((R)0.5, Pn[q] + Pr, pref[q]) : pref[q] + Pn[q];
+            // Magnus exponents of face and node (FP64: one shared reciprocal)
+            const R df = thf + (R)243.04, dn = thn + (R)243.04;
+            R af, an;
+            if constexpr (sizeof(R) == 8) {
+                const R inv = rcp_nr(df * dn);
+                af = (thf * dn) * inv;
+                an = (thn * df) * inv;
+            } else {
+                af = div_nr(thf, df);
+                an = div_nr(thn, dn);
+            }
+            const R ef = exp_bounded(-(R)17.625 * af);
+            const R en = exp_bounded(-(R)17.625 * an);
+            const R phi = (Pf * ef) * ps_inv;               // phi = P / Ps
+            phn[q] = ((pref[q] + Pn[q]) * en) * ps_inv;
+            kT[q] = live ? kf0[q] * fma(aT, phi, (R)1) : (R)0;
+            kM[q] = live ? kMf0[q] * fma(aM * phi, phi, (R)1) : (R)0;
             kX[q] = bTM * kM[q];
         }
         R *fp = facb + par * 3 * nthreads;
@@ -255,7 +300,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         fp[nthreads + t] = kM[NPT - 1];
         fp[2 * nthreads + t] = kX[NPT - 1];
         __syncthreads();
-        // ---- C: node updates
+        // ---- C: node updates (moisture, then heat with the new Pv)
         const R klT = t > 0 ? fp[t - 1] : (R)0;
         const R klM = t > 0 ? fp[nthreads + t - 1] : (R)0;
         const R klX = t > 0 ? fp[2 * nthreads + t - 1] : (R)0;
@@ -263,11 +308,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         for (int q = 0; q < NPT; ++q) {
             const int f = info[q];
             const R th = thref[q] + Tn[q];
-            const R P = pref[q] + Pn[q];
-            const R phi = P * magnus_exp_neg<R>(th) * (R)(1.0 / 610.94);
-            const R ccT = c0s[q] * ((R)1 + cT * phi);
-            const R ccM = cM0s[q] * ((R)1 + aC * phi);
-            const R ccX = (eTM + fTM * th) * ccM;
+            const R phi = phn[q];
+            const R ccT = c0s[q] * fma(cT, phi, (R)1);
+            const R ccM = cM0s[q] * fma(aC, phi, (R)1);
+            const R ccX = fma(fTM, th, eTM) * ccM;
             const R lT = q > 0 ? kT[q > 0 ? q - 1 : 0] : klT;
             const R lM = q > 0 ? kM[q > 0 ? q - 1 : 0] : klM;
             const R lX = q > 0 ? kX[q > 0 ? q - 1 : 0] : klX;
@@ -278,13 +322,24 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             R Tnew, Pnew;
             if (!(f & (3 << 8))) {
                 const R KM = lM + kM[q];
-                Pnew = ((ccM - KM) * Pm[q] + (R)2 * (kM[q] * Pr + lM * Pl)) / (ccM + KM);
                 const R KT = lT + kT[q];
                 const R KX = lX + kX[q];
-                const R rhs = (ccT - KT) * Tm[q] + (R)2 * (kT[q] * Tr + lT * Tl)
-                            + (ccX - KX) * Pm[q] - (ccX + KX) * Pnew
-                            + (R)2 * (kX[q] * Pr + lX * Pl);
-                Tnew = rhs / (ccT + KT);
+                const R dM = ccM + KM, dT = ccT + KT;
+                const R numM = fma(ccM - KM, Pm[q], (R)2 * fma(kM[q], Pr, lM * Pl));
+                R inv = 0;
+                if constexpr (sizeof(R) == 8) {
+                    inv = rcp_nr(dM * dT);
+                    Pnew = numM * (dT * inv);
+                } else {
+                    Pnew = div_nr(numM, dM);
+                }
+                const R rhs = fma(ccT - KT, Tm[q],
+                                  fma((R)2, fma(kT[q], Tr, lT * Tl),
+                                      fma(ccX - KX, Pm[q],
+                                          fma(-(ccX + KX), Pnew,
+                                              (R)2 * fma(kX[q], Pr, lX * Pl)))));
+                if constexpr (sizeof(R) == 8) Tnew = rhs * (dM * inv);
+                else Tnew = div_nr(rhs, dT);
             } else {
                 const int s = f & 0xff;
                 const int side = (f >> 8) & 1 ? 0 : 1;
@@ -294,16 +349,8 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const R k_X = side == 0 ? kX[q] : lX;
                 const R Tnb = side == 0 ? Tr : Tl;
                 const R Pnb = side == 0 ? Pr : Pl;
-                double Tinf, Pinf;
-                if (W.room >= 0 && W.room_side == side) {
-                    const int z = s_wroom[s];
-                    Tinf = s_room[par][z][0];
-                    Pinf = s_room[par][z][1];
-                } else {
-                    const double tt = (double)n * rc.dt;
-                    Tinf = sine_at(W.Tamb[side], tt);
-                    Pinf = sine_at(W.RHamb[side], tt) * psat_th(Tinf - 273.15);
-                }
+                const double Tinf = s_amb[par][s][side][0];
+                const double Pinf = s_amb[par][s][side][1];
                 const double tref = Store<R>::tref(W);
                 const R Tid = (R)(Tinf - tref);
                 const R Pid = (R)(Pinf - (double)pref[q]);
@@ -311,15 +358,28 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const R hT = (R)W.hT[side], hM = (R)W.hM[side];
                 const R hL = (R)(rc.Lv * W.hM[side]);
                 const R ginf = (R)W.ginf[side], qinf = (R)W.qinf[side];
-                Pnew = ((ccM - (R)2 * k_M - (R)2 * d * hM) * Pm[q] + (R)4 * k_M * Pnb
-                        + (R)4 * d * (hM * Pid + ginf))
-                     / (ccM + (R)2 * k_M + (R)2 * d * hM);
-                const R rhs = (ccT - (R)2 * k_T - (R)2 * d * hT) * Tm[q] + (R)4 * k_T * Tnb
-                            + (R)4 * d * hT * Tid
-                            + (ccX - (R)2 * k_X - (R)2 * d * hL) * Pm[q]
-                            - (ccX + (R)2 * k_X + (R)2 * d * hL) * Pnew
-                            + (R)4 * k_X * Pnb + (R)4 * d * hL * Pid + (R)4 * d * qinf;
-                Tnew = rhs / (ccT + (R)2 * k_T + (R)2 * d * hT);
+                const R gM = fma((R)2, k_M, (R)2 * d * hM);     // 2 r k + 2 s h (over r)
+                const R gT = fma((R)2, k_T, (R)2 * d * hT);
+                const R gX = fma((R)2, k_X, (R)2 * d * hL);
+                const R dM = ccM + gM;
+                const R dT = ccT + gT;
+                const R numM = fma(ccM - gM, Pm[q],
+                                   fma((R)4 * k_M, Pnb, (R)4 * d * fma(hM, Pid, ginf)));
+                R inv = 0;
+                if constexpr (sizeof(R) == 8) {
+                    inv = rcp_nr(dM * dT);
+                    Pnew = numM * (dT * inv);
+                } else {
+                    Pnew = div_nr(numM, dM);
+                }
+                const R rhs = fma(ccT - gT, Tm[q],
+                              fma((R)4 * k_T, Tnb,
+                              fma(ccX - gX, Pm[q],
+                              fma(-(ccX + gX), Pnew,
+                              fma((R)4 * k_X, Pnb,
+                                  (R)4 * d * fma(hT, Tid, fma(hL, Pid, qinf)))))));
+                if constexpr (sizeof(R) == 8) Tnew = rhs * (dM * inv);
+                else Tnew = div_nr(rhs, dT);
                 // applied flux (FP64) and its compensated integral
                 const double Ts = 0.5 * ((double)Tnew + (double)Tm[q]);
                 const double Ps = 0.5 * ((double)Pnew + (double)Pm[q]);
@@ -354,17 +414,15 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     for (int q = 0; q < NPT; ++q) {
         const int f = info[q];
         if (f & (1 << 10)) {
-        const int b = t * NPT + q;
-        const int s = f & 0xff;
-        const WallDev &W = walls[s_wid[s]];
-        const int64_t g = (int64_t)W.off + (b - s_wstart[s]);
-        const R Tcur = Tn[q], Pcur = Pn[q];
-        const R Tprv = Tm[q], Pprv = Pm[q];
-        if (!(isfinite(Tcur) && isfinite(Pcur))) nonfinite = 1;
-        Tw_cur[g] = Tcur;
-        Pw_cur[g] = Pcur;
-        Tw_prv[g] = Tprv;
-        Pw_prv[g] = Pprv;
+            const int b = t * NPT + q;
+            const int s = f & 0xff;
+            const WallDev &W = walls[s_wid[s]];
+            const int64_t g = (int64_t)W.off + (b - s_wstart[s]);
+            if (!(isfinite(Tn[q]) && isfinite(Pn[q]))) nonfinite = 1;
+            Tw_cur[g] = Tn[q];
+            Pw_cur[g] = Pn[q];
+            Tw_prv[g] = Tm[q];
+            Pw_prv[g] = Pm[q];
         }
     }
     if (nonfinite) atomicOr(bad, 1);

@@ -325,7 +325,7 @@ dfhm_status step_stream(dfhm_ctx *c, int64_t nsteps)
 
 struct Cand { int nt, npt; };
 // launch shapes the library is built for (threads, nodes per lane)
-const Cand kCands[] = {{256, 4}, {128, 8}, {256, 2}, {512, 2}, {128, 4}, {512, 4}, {256, 8}, {512, 8}};
+const Cand kCands[] = {{256, 4}, {256, 2}, {128, 4}, {512, 2}, {128, 8}, {512, 4}, {256, 8}};
 
 int effective_schedule(const dfhm_ctx *c)
 {
@@ -465,7 +465,7 @@ Cand default_shape(const dfhm_ctx *c)
     int need = max_group(c);
     for (const Cand &k : kCands)
         if (k.nt * k.npt >= need) return k;
-    return {512, 8};
+    return {256, 8};
 }
 
 dfhm_status ensure_packing(dfhm_ctx *c)
@@ -511,7 +511,7 @@ void launch_resident(dfhm_ctx *c, int k)
     const int nt = c->res_threads, npt = c->res_npt;
 #define DFHM_RES_CASE(T_, P_) if (nt == T_ && npt == P_) { launch_res<R, P_, T_>(c, k); return; }
     DFHM_RES_CASE(256, 4) DFHM_RES_CASE(128, 8) DFHM_RES_CASE(256, 2) DFHM_RES_CASE(512, 2)
-    DFHM_RES_CASE(128, 4) DFHM_RES_CASE(512, 4) DFHM_RES_CASE(256, 8) DFHM_RES_CASE(512, 8)
+    DFHM_RES_CASE(128, 4) DFHM_RES_CASE(512, 4) DFHM_RES_CASE(256, 8)
 #undef DFHM_RES_CASE
 }
 

@@ -112,6 +112,61 @@ __device__ __forceinline__ KCoef<R> face_k(const WallDev &W, int la, int lb, R t
     return k;
 }
 
+// ------------------------------------------------------- fast arithmetic
+// Reciprocal: hardware estimate refined by two Newton-Raphson steps
+// x <- x + x (1 - b x) (quadratic convergence; ~1 ulp in FP64).  FP32 keeps
+// the 1-ulp hardware estimate, well inside the FP32 path's error budget.
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double x = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-b, x, 1.0);
+    return fma(x, e, x);
+}
+__device__ __forceinline__ float rcp_nr(float b)
+{
+    float x = __builtin_amdgcn_rcpf(b);
+    return fmaf(x, fmaf(-b, x, 1.0f), x);
+}
+
+// a / b from the refined reciprocal plus one residual correction
+// q <- q + (a - b q) / b (within about one ulp of the rounded quotient).
+template <typename R>
+__device__ __forceinline__ R div_nr(R a, R b)
+{
+    const R x = rcp_nr(b);
+    const R q = a * x;
+    return fma(fma(-b, q, a), x, q);
+}
+
+// exp(a) for |a| well inside the FP64 range (no overflow / special-value
+// handling): Cody-Waite reduction a = k ln2 + r, |r| <= ln2/2, with ln2 split
+// into a 32-bit head and a tail, then the Taylor series of exp(r) to degree
+// 13 (truncation < 5e-18 relative) and a scaling by 2^k.
+__device__ __forceinline__ double exp_bounded(double a)
+{
+    const double k = rint(a * 1.4426950408889634074);
+    double r = fma(-k, 6.93147180369123816490e-01, a);
+    r = fma(-k, 1.90821492927058770002e-10, r);
+    double p = 1.6059043836821614599e-10;          // 1/13!
+    p = fma(p, r, 2.0876756987868098979e-09);      // 1/12!
+    p = fma(p, r, 2.5052108385441718775e-08);      // 1/11!
+    p = fma(p, r, 2.7557319223985890653e-07);      // 1/10!
+    p = fma(p, r, 2.7557319223985890653e-06);      // 1/9!
+    p = fma(p, r, 2.4801587301587301587e-05);      // 1/8!
+    p = fma(p, r, 1.9841269841269841270e-04);      // 1/7!
+    p = fma(p, r, 1.3888888888888888889e-03);      // 1/6!
+    p = fma(p, r, 8.3333333333333333333e-03);      // 1/5!
+    p = fma(p, r, 4.1666666666666666667e-02);      // 1/4!
+    p = fma(p, r, 1.6666666666666666667e-01);      // 1/3!
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)k);
+}
+__device__ __forceinline__ float exp_bounded(float a) { return __expf(a); }
+
 // Neumaier (1974) compensated accumulation.
 __device__ __forceinline__ void neumaier_add(double &s, double &c, double x)
 {
