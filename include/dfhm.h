@@ -198,6 +198,80 @@ dfhm_status dfhm_get_info(const dfhm_ctx *ctx, dfhm_info *info);
  * when it is set.  Allowed only at step index 0 or after a completed step. */
 dfhm_status dfhm_autotune(dfhm_ctx *ctx, int32_t probe_steps);
 
+/* ---------------------------------------------------------------------
+ * Surface-flux surrogate (not part of the paper): an MLP mapping a wall's
+ * recent outdoor history and parameters to the next interval's mean interior
+ * surface fluxes, with BF16 weights / activations and FP32 accumulation on
+ * the MFMA units, trained on histories the DF solver produces; the DF solve
+ * is its fallback.  Layers: n_in -> width (GELU) x depth -> n_out.  All
+ * device pointers are caller-owned; BF16 is stored as uint16 (round to
+ * nearest even).  Work is queued on cfg->stream.
+ * ------------------------------------------------------------------- */
+typedef struct dfhm_mlp dfhm_mlp;
+typedef struct {
+    int32_t n_in;          /* input features, multiple of 8 */
+    int32_t width;         /* hidden width, multiple of 8 */
+    int32_t depth;         /* hidden layers, 1..16 */
+    int32_t n_out;         /* outputs, 1..32 (training needs an even count) */
+    int32_t max_batch;     /* largest batch of one call, <= 4,194,304 */
+    int32_t act_pairs;     /* 0: hidden activations in BF16; 1: as BF16 pairs
+                              hi + lo (16 significant bits; the GEMMs after
+                              the first see them as 2 x width inputs against
+                              duplicated BF16 weights, twice the MFMA work) */
+    uint64_t seed;         /* weight initialisation (normal, std sqrt(2/fan_in)) */
+    float beta1, beta2, eps, weight_decay;   /* AdamW */
+    void *stream;          /* hipStream_t or NULL */
+} dfhm_mlp_config;
+
+dfhm_status dfhm_mlp_create(const dfhm_mlp_config *cfg, dfhm_mlp **out);
+int64_t dfhm_mlp_param_count(const dfhm_mlp *m);
+/* Parameters in logical order: for each layer W[n_out_l][n_in_l] row-major
+ * then b[n_out_l]; FP32 host arrays of dfhm_mlp_param_count values. */
+dfhm_status dfhm_mlp_get_params(dfhm_mlp *m, float *host);
+dfhm_status dfhm_mlp_set_params(dfhm_mlp *m, const float *host);
+/* y_dev[batch][n_out] (FP32) = network(x_dev[batch][n_in] BF16). */
+dfhm_status dfhm_mlp_forward(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, float *y_dev);
+/* Training loss for n_out = 2F outputs (means mu_f, then log variances s_f,
+ * f < F) and targets y_dev[batch][F] (FP32):
+ * L = mean_b sum_f [ r^2 + sg(r^2) exp(-s_f) + s_f ], r = y_f - mu_f,
+ * sg = no gradient (the means learn the targets, s_f learns the log of the
+ * expected squared residual; the s_f train the output layer only, the
+ * hidden layers learn from the means alone).  DFHM_E_STATE if n_out is odd.  gradients:
+ * FP32 host array in logical order; loss (host) may be NULL. */
+dfhm_status dfhm_mlp_gradients(dfhm_mlp *m, const uint16_t *x_dev, const float *y_dev,
+                               int64_t batch, float *grad_host, float *loss);
+/* One AdamW step with learning rate lr on the loss above. */
+dfhm_status dfhm_mlp_train_step(dfhm_mlp *m, const uint16_t *x_dev, const float *y_dev,
+                                int64_t batch, float lr, float *loss);
+const char *dfhm_mlp_last_error(const dfhm_mlp *m);
+void dfhm_mlp_destroy(dfhm_mlp *m);
+
+/* Feature rows for the surrogate: for sample s of wall wall_dev[s] at time
+ * t_dev[s] (s): n_hist samples every dt_hist of the side-0 outdoor T and RH
+ * ending at t (oldest first), then 5 wall parameters params_dev[w][5] and 3
+ * time features (t / 1 day, sin and cos of the time of day), each z-scored
+ * with the given means / scales, zero-padded to stride (BF16).  sines_dev[w]
+ * = (T mean, amp, period, phase, RH mean, amp, period, phase). */
+typedef struct {
+    int32_t n_hist, stride;
+    float dt_hist, T_mean, T_scale, RH_mean, RH_scale;
+    float p_mean[8], p_scale[8];
+} dfhm_feature_desc;
+dfhm_status dfhm_mlp_features(const int32_t *wall_dev, const double *t_dev, const double *sines_dev,
+                              const float *params_dev, int64_t nsamp, const dfhm_feature_desc *fd,
+                              uint16_t *x_dev, void *stream);
+/* Decode the flux head (n_out = 8): per field f (heat, vapour) the network
+ * predicts u_f = flux / RMS flux of the wall over the prediction windows and
+ * l_f = log(RMS flux), normalised as value = mean + std * output with host
+ * scale[8] = {mean, std} of u_q, u_g, l_q, l_g; outputs y_dev[b] = (u_q, u_g,
+ * l_q, l_g, then their log variances).  flux_dev[b][f] = u_f exp(l_f) (heat
+ * W/m2, vapour kg/(m2 s)); fallback_dev[b] = 1 when the predicted error
+ * relative to the RMS flux, sd(u_f) + |u_f| sd(l_f), exceeds tau for either
+ * field: those samples go back to the DF solver.  DFHM_E_INVAL on a
+ * non-positive std or tau. */
+dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scale, float tau,
+                            float *flux_dev, uint8_t *fallback_dev, void *stream);
+
 int64_t dfhm_step_index(const dfhm_ctx *ctx);
 const char *dfhm_last_error(const dfhm_ctx *ctx);
 const char *dfhm_status_string(dfhm_status s);

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "dfhm_api.hip")
+SRCS = [os.path.join(HERE, "csrc", "dfhm_api.hip"), os.path.join(HERE, "csrc", "mlp_api.hip")]
 LIB = os.path.join(HERE, "libdfhm.so")
 
 HIPCC_FLAGS = [
@@ -23,7 +23,7 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, SRC, "-o", tmp]
+    cmd = ["hipcc", *HIPCC_FLAGS, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

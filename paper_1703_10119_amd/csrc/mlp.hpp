@@ -1,0 +1,334 @@
+// mlp.hpp -- kernels of the surface-flux surrogate: BF16 MFMA GEMMs with
+// FP32 accumulation and fused epilogues, reductions, loss, AdamW and the
+// feature builder (gfx950).
+//
+// The network maps a 48 h outdoor history and wall parameters to the next
+// 10-min mean interior surface fluxes; it is not part of the paper.  All
+// matrices are row-major; BF16 values are stored as uint16 (round to nearest
+// even from FP32).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfhm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0;   // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// GELU and its derivative (erf form).
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float z)
+{
+    const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+    const float pdf = 0.39894228040143268f * __expf(-0.5f * z * z);
+    return cdf + z * pdf;
+}
+
+// Operand layouts.  For C[m][n] = sum_k A(m,k) B(k,n):
+//   A: OP_K  -> A[m * lda + k] (reduction index contiguous)
+//      OP_MN -> A[k * lda + m]
+//   B: OP_K  -> B[n * ldb + k]
+//      OP_MN -> B[k * ldb + n]
+enum { OP_K = 0, OP_MN = 1 };
+// Epilogues.
+enum {
+    EPI_F32 = 0,        // Cf[z][m][n] = acc (split-K partials when gridDim.z > 1)
+    EPI_BIAS_F32 = 1,   // Cf[m][n] = acc + bias[n]
+    EPI_BIAS_GELU = 2,  // z = acc + bias[n]: pre[m][n] = bf16(z), Cb[m][n] = bf16(gelu(z))
+    EPI_GELU_BWD = 3,   // Cb[m][n] = bf16(acc * gelu'(aux[m][n]))
+    EPI_BIAS_GELU2 = 4  // as EPI_BIAS_GELU, storing gelu(z) as a BF16 pair:
+                        // Cb[m][n] = hi = bf16(g), Cb[m][N + n] = bf16(g - hi)
+};
+
+constexpr int GB_M = 128, GB_N = 128, GB_K = 32, G_PAD = 8;
+
+// Load a 128 x 32 tile of an operand into LDS as [row][k] (k contiguous).
+// rows = M or N index, K multiple of 8, rows multiple of 8 (zero outside).
+template <int LAYOUT>
+__device__ __forceinline__ void load_tile(uint16_t (*s)[GB_K + G_PAD], const uint16_t *__restrict__ g,
+                                          int ld, int row0, int nrows, int k0, int kend, int tid)
+{
+    if (LAYOUT == OP_K) {
+        const int r = tid >> 1;                 // 128 rows, 2 threads per row
+        const int kk = (tid & 1) * 16;
+        const int gr = row0 + r;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gk = k0 + kk + 8 * h;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gr < nrows && gk < kend) v = *(const uint4 *)(g + (int64_t)gr * ld + gk);
+            *(uint4 *)&s[r][kk + 8 * h] = v;
+        }
+    } else {
+        const int kk = tid >> 3;                // 32 k, 8 threads per k
+        const int rr = (tid & 7) * 16;
+        const int gk = k0 + kk;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gr = row0 + rr + 8 * h;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gr < nrows && gk < kend) v = *(const uint4 *)(g + (int64_t)gk * ld + gr);
+            const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s[rr + 8 * h + q][kk] = e[q];
+        }
+    }
+}
+
+// One 128 x 128 output tile per workgroup of 256 lanes (2 x 2 waves of
+// 64 x 64, each a 4 x 4 grid of 16 x 16 MFMA tiles, K step 32).  Split-K:
+// blockIdx.z covers K range [z * kchunk, (z+1) * kchunk).
+template <int LA, int LB, int EPI>
+__global__ void __launch_bounds__(256)
+k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
+            const uint16_t *__restrict__ B, int ldb, float *__restrict__ Cf,
+            uint16_t *__restrict__ Cb, int ldc, const float *__restrict__ bias,
+            const uint16_t *__restrict__ aux, uint16_t *__restrict__ pre, int kchunk)
+{
+    __shared__ __align__(16) uint16_t sA[GB_M][GB_K + G_PAD];
+    __shared__ __align__(16) uint16_t sB[GB_N][GB_K + G_PAD];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * GB_M, n0 = blockIdx.x * GB_N;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    const int fr = lane & 15;          // row (A) / column (B) inside a 16 x 16 tile
+    const int fk = (lane >> 4) * 8;    // this lane's 8 reduction indices
+    for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
+        load_tile<LA>(sA, A, lda, m0, M, k0, kend, tid);
+        load_tile<LB>(sB, B, ldb, n0, N, k0, kend, tid);
+        __syncthreads();
+        bf16x8 af[4], bfr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8 *)&sA[wm * 64 + i * 16 + fr][fk];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bfr[j] = *(const bf16x8 *)&sB[wn * 64 + j * 16 + fr][fk];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // accumulator layout: lane holds rows 4*(lane/16)+r, column lane%16
+    const int rbase = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 64 + i * 16 + rbase + r;
+                const int col = n0 + wn * 64 + j * 16 + fr;
+                if (row >= M || col >= N) continue;
+                const float v = acc[i][j][r];
+                const int64_t o = (int64_t)row * ldc + col;
+                if (EPI == EPI_F32) {
+                    Cf[(int64_t)blockIdx.z * M * ldc + o] = v;
+                } else if (EPI == EPI_BIAS_F32) {
+                    Cf[o] = v + bias[col];
+                } else if (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS_GELU2) {
+                    const float z = v + bias[col];
+                    const float g = gelu(z);
+                    const uint16_t hi = f2bf(g);
+                    pre[(int64_t)row * N + col] = f2bf(z);
+                    Cb[o] = hi;
+                    if (EPI == EPI_BIAS_GELU2) Cb[o + N] = f2bf(g - bf2f(hi));
+                } else {
+                    Cb[o] = f2bf(v * gelu_d(bf2f(aux[o])));
+                }
+            }
+}
+
+// Sum of split-K partials: out[i] = sum_z part[z][i] (+ out[i] if accumulate).
+__global__ void k_sum_partials(const float *__restrict__ part, int nsplit, int64_t n, float *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * n + i];
+    out[i] = s;
+}
+
+// Column sums of a BF16 matrix [rows][cols] into FP32 partials
+// part[blockIdx.y][col] over row range blockIdx.y * rchunk ...
+__global__ void k_colsum_bf16(const uint16_t *__restrict__ x, int rows, int cols, int rchunk,
+                              float *__restrict__ part)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= cols) return;
+    const int r0 = blockIdx.y * rchunk, r1 = min(rows, r0 + rchunk);
+    float s = 0.f;
+    for (int r = r0; r < r1; ++r) s += bf2f(x[(int64_t)r * cols + col]);
+    part[(int64_t)blockIdx.y * cols + col] = s;
+}
+
+// Loss of a head with F = n_out / 2 targets: outputs z[b][0..F) are the
+// means, z[b][F..2F) the log variances, targets y[b][0..F) (normalised).
+// Mean squared error on the means plus a Gaussian log-likelihood term for
+// the log variances with the residual held fixed:
+//   L = (1/B) sum_b sum_f [ r^2 + sg(r^2) exp(-s) + s ],  r = y - mu.
+// Writes dZ[b][0..ldz) as BF16 (zeros beyond the 2F outputs) and per-block
+// partial losses.
+__global__ void k_loss(const float *__restrict__ z, int ldz, const float *__restrict__ y, int B,
+                       int F, uint16_t *__restrict__ dz, float *__restrict__ part)
+{
+    __shared__ float red[256];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.f;
+    if (b < B) {
+        const float invB = 1.0f / (float)B;
+        for (int f = 0; f < F; ++f) {
+            const float mu = z[(int64_t)b * ldz + f];
+            const float s = z[(int64_t)b * ldz + F + f];
+            const float r = y[(int64_t)F * b + f] - mu;
+            const float e = __expf(-s);
+            l += r * r + r * r * e + s;
+            dz[(int64_t)b * ldz + f] = f2bf(-2.0f * r * invB);
+            dz[(int64_t)b * ldz + F + f] = f2bf((1.0f - r * r * e) * invB);
+        }
+        for (int f = 2 * F; f < ldz; ++f) dz[(int64_t)b * ldz + f] = 0;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Zero columns [c0, c1) of a BF16 matrix [rows][ld].
+__global__ void k_zero_cols(uint16_t *__restrict__ x, int rows, int ld, int c0, int c1)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = c1 - c0;
+    if (i >= (int64_t)rows * w) return;
+    x[(i / w) * ld + c0 + i % w] = 0;
+}
+
+// AdamW on FP32 master weights (the BF16 copies are packed afterwards).
+// mask[i] = 0 keeps a padding weight at zero.
+__global__ void k_adamw(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                        const float *__restrict__ g, const uint8_t *__restrict__ mask, int64_t n,
+                        float lr, float b1, float b2, float eps, float wd, float c1, float c2)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (mask && !mask[i]) { w[i] = 0.f; return; }
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi * c1, vh = vi * c2;     // bias corrections 1/(1 - b^t)
+    float wi = w[i];
+    wi -= lr * (mh / (sqrtf(vh) + eps) + wd * wi);
+    w[i] = wi;
+}
+
+// BF16 copy of a weight matrix w[N][K] (FP32) as wb[N][ld]; with dup the row
+// is stored twice, wb[n][k] = wb[n][K + k], the weight operand of a layer
+// whose input is a BF16 pair (hi | lo).
+__global__ void k_pack_weights(const float *__restrict__ w, uint16_t *__restrict__ wb, int N, int K,
+                               int ld, int dup)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * K) return;
+    const int64_t n = i / K, k = i % K;
+    const uint16_t h = f2bf(w[i]);
+    wb[n * ld + k] = h;
+    if (dup) wb[n * ld + K + k] = h;
+}
+
+// Features of one sample: the outdoor temperature and humidity of side 0
+// sampled every `dt_hist` seconds over the n_hist samples ending at time t
+// (oldest first), z-scored, then 8 parameters, z-scored -- 5 per wall
+// (params[w][0..4]) and 3 of the time (t / 1 day, sin and cos of the time of
+// day) -- then zeros up to the row stride.  Inputs per sample: wall, time.
+struct FeatDesc {
+    int n_hist, stride;
+    float dt_hist, T_mean, T_scale, RH_mean, RH_scale;
+    float p_mean[8], p_scale[8];
+};
+
+__global__ void k_features(const int32_t *__restrict__ wall_of, const double *__restrict__ t_of,
+                           const double *__restrict__ sines /* [W][8]: T mean, amp, period, phase, RH ... */,
+                           const float *__restrict__ params /* [W][5] */, int nsamp, FeatDesc fd,
+                           uint16_t *__restrict__ x)
+{
+    const int s = blockIdx.x;
+    if (s >= nsamp) return;
+    const int w = wall_of[s];
+    const double t = t_of[s];
+    const double *S = sines + (int64_t)w * 8;
+    uint16_t *row = x + (int64_t)s * fd.stride;
+    for (int i = threadIdx.x; i < fd.stride; i += blockDim.x) {
+        float v = 0.f;
+        if (i < 2 * fd.n_hist) {
+            const int h = i < fd.n_hist ? i : i - fd.n_hist;
+            const double *q = i < fd.n_hist ? S : S + 4;
+            const double ts = t - (double)(fd.n_hist - 1 - h) * (double)fd.dt_hist;
+            double ph = fmod(2.0 * 3.14159265358979323846 * ts / q[2] + q[3], 2.0 * 3.14159265358979323846);
+            const float val = (float)(q[0] + q[1] * sin(ph));
+            v = i < fd.n_hist ? (val - fd.T_mean) / fd.T_scale : (val - fd.RH_mean) / fd.RH_scale;
+        } else if (i < 2 * fd.n_hist + 8) {
+            const int p = i - 2 * fd.n_hist;
+            float raw;
+            if (p < 5) raw = params[(int64_t)w * 5 + p];
+            else if (p == 5) raw = (float)(t / 86400.0);
+            else {
+                const double ph = 2.0 * 3.14159265358979323846 * fmod(t, 86400.0) / 86400.0;
+                raw = (float)(p == 6 ? sin(ph) : cos(ph));
+            }
+            v = (raw - fd.p_mean[p]) / fd.p_scale[p];
+        }
+        row[i] = f2bf(v);
+    }
+}
+
+// Decode the flux head.  Per field f (heat, vapour) the network predicts
+// the flux relative to the wall's RMS flux, u_f, and the log of that RMS,
+// l_f, each normalised (value = mean + std * output); outputs
+// y[b] = (u_q, u_g, l_q, l_g, s_uq, s_ug, s_lq, s_lg), s = log variance.
+// flux_f = u_f exp(l_f).  The predicted error relative to the RMS flux is
+// e_f = sd(u_f) + |u_f| sd(l_f) to first order, sd = std * exp(s / 2);
+// fallback when e_f > tau for either field.  scale[8] = (mean, std) of
+// u_q, u_g, l_q, l_g.
+struct DecodeScale { float m[4], s[4]; };
+
+__global__ void k_decode(const float *__restrict__ y, int64_t batch, DecodeScale sc, float tau,
+                         float *__restrict__ flux, uint8_t *__restrict__ fallback)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const float *o = y + 8 * b;
+    bool fb = false;
+    for (int f = 0; f < 2; ++f) {
+        const float u = o[f] * sc.s[f] + sc.m[f];
+        const float lg = o[2 + f] * sc.s[2 + f] + sc.m[2 + f];
+        flux[2 * b + f] = u * __expf(lg);
+        const float e = sc.s[f] * __expf(0.5f * o[4 + f]) + fabsf(u) * sc.s[2 + f] * __expf(0.5f * o[6 + f]);
+        fb = fb || !(e <= tau);
+    }
+    fallback[b] = (uint8_t)fb;
+}
+
+} // namespace dfhm

@@ -1,0 +1,413 @@
+// mlp_api.hip -- host side of the surface-flux surrogate (dfhm_mlp_* in
+// include/dfhm.h).  Device memory: FP32 master weights, BF16 copies, AdamW
+// moments, gradients, activations (BF16) and pre-activations (BF16) of every
+// layer for the largest batch, split-K partials.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/dfhm.h"
+#include "mlp.hpp"
+
+using namespace dfhm;
+
+namespace {
+constexpr int kOutPad = 32;   // output layer rows padded for the GEMM tiles
+
+struct Layer {
+    int K, N, Np;             // inputs, logical outputs, padded outputs
+    int Kx;                   // reduction length of the forward GEMM: 2K for a BF16-pair input
+    size_t w_off, b_off;      // offsets into the flat FP32 parameter buffer
+    size_t wb_off;            // offset of the BF16 weight operand [Np][Kx]
+};
+} // namespace
+
+struct dfhm_mlp {
+    dfhm_mlp_config cfg{};
+    hipStream_t stream = nullptr;
+    std::vector<Layer> layers;
+    int64_t n_params = 0;      // logical parameters (exposed)
+    int64_t n_dev = 0;         // device parameters (with padding)
+    int64_t n_wb = 0;          // BF16 weight operands
+    bool pairs = false;        // hidden activations as BF16 pairs
+    float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    uint16_t *wb = nullptr;
+    uint8_t *mask = nullptr;
+    std::vector<uint16_t *> act;   // act[0] = input (caller's), act[l+1] = output of layer l
+                                   // ([B][N], or [B][2N] = hi | lo with pairs)
+    std::vector<uint16_t *> pre;   // pre-activations of hidden layers
+    std::vector<uint16_t *> dact;  // gradients w.r.t. layer outputs (BF16)
+    float *out = nullptr;          // output layer result [B][kOutPad] FP32
+    float *part = nullptr;         // split-K partials / column sums
+    size_t part_n = 0;
+    float *loss_part = nullptr;
+    int64_t step = 0;
+    std::vector<void *> allocs;
+    std::string err;
+};
+
+namespace {
+
+dfhm_status mfail(dfhm_mlp *m, dfhm_status s, const std::string &msg)
+{
+    if (m) m->err = msg;
+    return s;
+}
+
+#define MHIP(mm, call)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return mfail((mm), DFHM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+dfhm_status dalloc(dfhm_mlp *m, T **p, size_t n)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * (n ? n : 1)) != hipSuccess) return mfail(m, DFHM_E_NOMEM, "mlp buffers");
+    m->allocs.push_back(q);
+    *p = (T *)q;
+    return DFHM_OK;
+}
+
+template <int LA, int LB, int EPI>
+void gemm(dfhm_mlp *m, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
+          float *Cf, uint16_t *Cb, int ldc, const float *bias, const uint16_t *aux, uint16_t *pre,
+          int nsplit)
+{
+    const int kchunk = ((K + nsplit - 1) / nsplit + GB_K - 1) / GB_K * GB_K;
+    dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, nsplit);
+    hipLaunchKernelGGL((k_gemm_bf16<LA, LB, EPI>), grid, dim3(256), 0, m->stream, M, N, K, A, lda,
+                       B, ldb, Cf, Cb, ldc, bias, aux, pre, kchunk);
+}
+
+int blocks_of(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+// Forward pass over `batch` rows; leaves the output layer in m->out.
+void forward(dfhm_mlp *m, const uint16_t *x, int batch)
+{
+    const int L = (int)m->layers.size();
+    m->act[0] = const_cast<uint16_t *>(x);
+    for (int l = 0; l < L; ++l) {
+        const Layer &ly = m->layers[l];
+        const uint16_t *W = m->wb + ly.wb_off;
+        const float *b = m->w + ly.b_off;
+        if (l < L - 1 && m->pairs)
+            gemm<OP_K, OP_K, EPI_BIAS_GELU2>(m, batch, ly.N, ly.Kx, m->act[l], ly.Kx, W, ly.Kx,
+                                             nullptr, m->act[l + 1], 2 * ly.N, b, nullptr, m->pre[l], 1);
+        else if (l < L - 1)
+            gemm<OP_K, OP_K, EPI_BIAS_GELU>(m, batch, ly.N, ly.Kx, m->act[l], ly.Kx, W, ly.Kx, nullptr,
+                                            m->act[l + 1], ly.N, b, nullptr, m->pre[l], 1);
+        else
+            gemm<OP_K, OP_K, EPI_BIAS_F32>(m, batch, ly.Np, ly.Kx, m->act[l], ly.Kx, W, ly.Kx, m->out,
+                                           nullptr, ly.Np, b, nullptr, nullptr, 1);
+    }
+}
+
+// Backward pass from dact[L-1] (= dL/dz of the output layer, BF16 [B][Np])
+// into m->g (FP32, device layout).
+void backward(dfhm_mlp *m, int batch)
+{
+    const int L = (int)m->layers.size();
+    for (int l = L - 1; l >= 0; --l) {
+        const Layer &ly = m->layers[l];
+        const int Nl = l == L - 1 ? ly.Np : ly.N;
+        const uint16_t *dz = m->dact[l];
+        // weight gradient dW[N][K] = dz^T [N][B] . act[l] [B][K] (the hi half of a pair),
+        // split over the batch
+        int nsplit = std::max(1, std::min(16, batch / 512));
+        gemm<OP_MN, OP_MN, EPI_F32>(m, Nl, ly.K, batch, dz, Nl, m->act[l], ly.Kx, m->part, nullptr,
+                                    ly.K, nullptr, nullptr, nullptr, nsplit);
+        const int64_t nw = (int64_t)Nl * ly.K;
+        hipLaunchKernelGGL(k_sum_partials, dim3(blocks_of(nw, 256)), dim3(256), 0, m->stream,
+                           m->part, nsplit, nw, m->g + ly.w_off);
+        // bias gradient: column sums of dz
+        const int rchunk = 256;
+        const int nrc = (batch + rchunk - 1) / rchunk;
+        float *cs = m->part + (size_t)nsplit * nw;
+        hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks_of(Nl, 64), nrc), dim3(64), 0, m->stream, dz,
+                           batch, Nl, rchunk, cs);
+        hipLaunchKernelGGL(k_sum_partials, dim3(blocks_of(Nl, 256)), dim3(256), 0, m->stream, cs,
+                           nrc, (int64_t)Nl, m->g + ly.b_off);
+        // the log-variance outputs train the output layer only
+        if (l == L - 1 && l > 0) {
+            const int F = m->cfg.n_out / 2;
+            hipLaunchKernelGGL(k_zero_cols, dim3(blocks_of((int64_t)batch * F, 256)), dim3(256), 0,
+                               m->stream, m->dact[l], batch, Nl, F, 2 * F);
+        }
+        // input gradient through the previous GELU: dz_{l-1} = (dz . W) * gelu'(pre_{l-1})
+        if (l > 0) {
+            const uint16_t *W = m->wb + ly.wb_off;
+            gemm<OP_K, OP_MN, EPI_GELU_BWD>(m, batch, ly.K, Nl, dz, Nl, W, ly.Kx, nullptr,
+                                            m->dact[l - 1], ly.K, nullptr, m->pre[l - 1], nullptr, 1);
+        }
+    }
+}
+
+dfhm_status loss_and_grad(dfhm_mlp *m, const uint16_t *x, const float *y, int batch, float *loss)
+{
+    forward(m, x, batch);
+    const int L = (int)m->layers.size();
+    const int nb = blocks_of(batch, 256);
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, m->stream, m->out, kOutPad, y, batch,
+                       m->cfg.n_out / 2, m->dact[L - 1], m->loss_part);
+    backward(m, batch);
+    MHIP(m, hipGetLastError());
+    if (loss) {
+        std::vector<float> p(nb);
+        MHIP(m, hipMemcpyAsync(p.data(), m->loss_part, sizeof(float) * nb, hipMemcpyDeviceToHost, m->stream));
+        MHIP(m, hipStreamSynchronize(m->stream));
+        double s = 0;
+        for (float q : p) s += q;
+        *loss = (float)(s / batch);
+    }
+    return DFHM_OK;
+}
+
+// logical <-> device parameter layout (the output layer is padded)
+void to_logical(const dfhm_mlp *m, const std::vector<float> &dev, float *out)
+{
+    size_t o = 0;
+    for (const Layer &ly : m->layers) {
+        for (int n = 0; n < ly.N; ++n)
+            for (int k = 0; k < ly.K; ++k) out[o++] = dev[ly.w_off + (size_t)n * ly.K + k];
+        for (int n = 0; n < ly.N; ++n) out[o++] = dev[ly.b_off + n];
+    }
+}
+void to_device(const dfhm_mlp *m, const float *in, std::vector<float> &dev)
+{
+    std::fill(dev.begin(), dev.end(), 0.f);
+    size_t o = 0;
+    for (const Layer &ly : m->layers) {
+        for (int n = 0; n < ly.N; ++n)
+            for (int k = 0; k < ly.K; ++k) dev[ly.w_off + (size_t)n * ly.K + k] = in[o++];
+        for (int n = 0; n < ly.N; ++n) dev[ly.b_off + n] = in[o++];
+    }
+}
+
+// BF16 weight operands from the FP32 master weights
+void pack_weights(dfhm_mlp *m)
+{
+    for (const Layer &ly : m->layers)
+        hipLaunchKernelGGL(k_pack_weights, dim3(blocks_of((int64_t)ly.Np * ly.K, 256)), dim3(256), 0,
+                           m->stream, m->w + ly.w_off, m->wb + ly.wb_off, ly.Np, ly.K, ly.Kx,
+                           (int)(ly.Kx != ly.K));
+}
+
+dfhm_status upload(dfhm_mlp *m, const std::vector<float> &dev)
+{
+    MHIP(m, hipMemcpyAsync(m->w, dev.data(), sizeof(float) * dev.size(), hipMemcpyHostToDevice, m->stream));
+    pack_weights(m);
+    MHIP(m, hipGetLastError());
+    MHIP(m, hipStreamSynchronize(m->stream));
+    return DFHM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+dfhm_status dfhm_mlp_create(const dfhm_mlp_config *cfg, dfhm_mlp **out)
+{
+    if (!out) return DFHM_E_INVAL;
+    *out = nullptr;
+    if (!cfg || cfg->n_in < 8 || cfg->n_in % 8 || cfg->width < 8 || cfg->width % 8 ||
+        cfg->depth < 1 || cfg->depth > 16 || cfg->n_out < 1 || cfg->n_out > kOutPad ||
+        cfg->max_batch < 1 || cfg->max_batch > (1 << 22) || cfg->act_pairs < 0 || cfg->act_pairs > 1)
+        return DFHM_E_INVAL;
+    dfhm_mlp *m = new (std::nothrow) dfhm_mlp();
+    if (!m) return DFHM_E_NOMEM;
+    m->cfg = *cfg;
+    m->stream = (hipStream_t)cfg->stream;
+    m->pairs = cfg->act_pairs == 1;
+    size_t o = 0, ob = 0;
+    int K = cfg->n_in;
+    for (int l = 0; l <= cfg->depth; ++l) {
+        Layer ly;
+        ly.K = K;
+        ly.Kx = (m->pairs && l > 0) ? 2 * K : K;
+        ly.N = l < cfg->depth ? cfg->width : cfg->n_out;
+        ly.Np = l < cfg->depth ? ly.N : kOutPad;
+        ly.w_off = o; o += (size_t)ly.Np * ly.K;
+        ly.b_off = o; o += (size_t)ly.Np;
+        ly.wb_off = ob; ob += (size_t)ly.Np * ly.Kx;
+        m->n_params += (int64_t)ly.N * ly.K + ly.N;
+        m->layers.push_back(ly);
+        K = ly.N;
+    }
+    m->n_dev = (int64_t)o;
+    m->n_wb = (int64_t)ob;
+    const int B = cfg->max_batch, L = (int)m->layers.size();
+    auto bail = [&](dfhm_status s) { dfhm_mlp_destroy(m); return s; };
+    if (dalloc(m, &m->w, o) || dalloc(m, &m->m, o) || dalloc(m, &m->v, o) || dalloc(m, &m->g, o) ||
+        dalloc(m, &m->wb, ob) || dalloc(m, &m->mask, o) || dalloc(m, &m->out, (size_t)B * kOutPad) ||
+        dalloc(m, &m->loss_part, (size_t)(B + 255) / 256))
+        return bail(DFHM_E_NOMEM);
+    m->act.assign(L + 1, nullptr);
+    m->pre.assign(L, nullptr);
+    m->dact.assign(L, nullptr);
+    size_t maxw = 0;
+    for (int l = 0; l < L; ++l) {
+        const Layer &ly = m->layers[l];
+        const int Nl = l == L - 1 ? ly.Np : ly.N;
+        if (l < L - 1) {
+            if (dalloc(m, &m->act[l + 1], (size_t)B * ly.N * (m->pairs ? 2 : 1)) ||
+                dalloc(m, &m->pre[l], (size_t)B * ly.N))
+                return bail(DFHM_E_NOMEM);
+        }
+        if (dalloc(m, &m->dact[l], (size_t)B * Nl)) return bail(DFHM_E_NOMEM);
+        maxw = std::max(maxw, (size_t)Nl * ly.K);
+    }
+    const size_t maxn = (size_t)std::max(cfg->width, kOutPad);
+    m->part_n = 16 * maxw + (size_t)((B + 255) / 256) * maxn + 1024;
+    if (dalloc(m, &m->part, m->part_n)) return bail(DFHM_E_NOMEM);
+    // He-style initialisation from the seed; biases zero; padding rows zero
+    std::mt19937_64 rng(cfg->seed);
+    std::vector<float> dev(o, 0.f);
+    std::vector<uint8_t> mask(o, 0);
+    for (int l = 0; l < L; ++l) {
+        const Layer &ly = m->layers[l];
+        std::normal_distribution<double> nd(0.0, std::sqrt((l < L - 1 ? 2.0 : 1.0) / ly.K));
+        for (int n = 0; n < ly.N; ++n) {
+            for (int k = 0; k < ly.K; ++k) {
+                dev[ly.w_off + (size_t)n * ly.K + k] = (float)nd(rng);
+                mask[ly.w_off + (size_t)n * ly.K + k] = 1;
+            }
+            mask[ly.b_off + n] = 1;
+        }
+    }
+    if (hipMemsetAsync(m->m, 0, sizeof(float) * o, m->stream) != hipSuccess ||
+        hipMemsetAsync(m->v, 0, sizeof(float) * o, m->stream) != hipSuccess ||
+        hipMemsetAsync(m->g, 0, sizeof(float) * o, m->stream) != hipSuccess ||
+        hipMemcpyAsync(m->mask, mask.data(), o, hipMemcpyHostToDevice, m->stream) != hipSuccess)
+        return bail(DFHM_E_DEVICE);
+    if (upload(m, dev)) return bail(DFHM_E_DEVICE);
+    *out = m;
+    return DFHM_OK;
+}
+
+int64_t dfhm_mlp_param_count(const dfhm_mlp *m) { return m ? m->n_params : -1; }
+
+dfhm_status dfhm_mlp_get_params(dfhm_mlp *m, float *host)
+{
+    if (!m || !host) return DFHM_E_INVAL;
+    std::vector<float> dev(m->n_dev);
+    MHIP(m, hipMemcpyAsync(dev.data(), m->w, sizeof(float) * m->n_dev, hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipStreamSynchronize(m->stream));
+    to_logical(m, dev, host);
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_mlp_set_params(dfhm_mlp *m, const float *host)
+{
+    if (!m || !host) return DFHM_E_INVAL;
+    for (int64_t i = 0; i < m->n_params; ++i)
+        if (!std::isfinite(host[i])) return mfail(m, DFHM_E_INVAL, "non-finite parameter");
+    std::vector<float> dev(m->n_dev);
+    to_device(m, host, dev);
+    return upload(m, dev);
+}
+
+dfhm_status dfhm_mlp_forward(dfhm_mlp *m, const uint16_t *x, int64_t batch, float *y)
+{
+    if (!m || !x || !y) return DFHM_E_INVAL;
+    if (batch < 1 || batch > m->cfg.max_batch) return mfail(m, DFHM_E_INVAL, "batch out of range");
+    forward(m, x, (int)batch);
+    // compact the padded output rows into y[batch][n_out]
+    MHIP(m, hipMemcpy2DAsync(y, sizeof(float) * m->cfg.n_out, m->out, sizeof(float) * kOutPad,
+                             sizeof(float) * m->cfg.n_out, batch, hipMemcpyDeviceToDevice, m->stream));
+    MHIP(m, hipGetLastError());
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_mlp_gradients(dfhm_mlp *m, const uint16_t *x, const float *y, int64_t batch,
+                               float *grad_host, float *loss)
+{
+    if (!m || !x || !y || !grad_host) return DFHM_E_INVAL;
+    if (m->cfg.n_out % 2) return mfail(m, DFHM_E_STATE, "the training loss needs an even n_out");
+    if (batch < 1 || batch > m->cfg.max_batch) return mfail(m, DFHM_E_INVAL, "batch out of range");
+    dfhm_status s = loss_and_grad(m, x, y, (int)batch, loss);
+    if (s) return s;
+    std::vector<float> dev(m->n_dev);
+    MHIP(m, hipMemcpyAsync(dev.data(), m->g, sizeof(float) * m->n_dev, hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipStreamSynchronize(m->stream));
+    to_logical(m, dev, grad_host);
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_mlp_train_step(dfhm_mlp *m, const uint16_t *x, const float *y, int64_t batch,
+                                float lr, float *loss)
+{
+    if (!m || !x || !y) return DFHM_E_INVAL;
+    if (m->cfg.n_out % 2) return mfail(m, DFHM_E_STATE, "the training loss needs an even n_out");
+    if (batch < 1 || batch > m->cfg.max_batch || !(lr >= 0.f))
+        return mfail(m, DFHM_E_INVAL, "batch or learning rate out of range");
+    dfhm_status s = loss_and_grad(m, x, y, (int)batch, loss);
+    if (s) return s;
+    m->step += 1;
+    const float b1 = m->cfg.beta1, b2 = m->cfg.beta2;
+    const float c1 = 1.0f / (1.0f - std::pow(b1, (float)m->step));
+    const float c2 = 1.0f / (1.0f - std::pow(b2, (float)m->step));
+    hipLaunchKernelGGL(k_adamw, dim3(blocks_of(m->n_dev, 256)), dim3(256), 0, m->stream, m->w, m->m,
+                       m->v, m->g, m->mask, m->n_dev, lr, b1, b2, m->cfg.eps,
+                       m->cfg.weight_decay, c1, c2);
+    pack_weights(m);
+    MHIP(m, hipGetLastError());
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_mlp_features(const int32_t *wall_dev, const double *t_dev, const double *sines_dev,
+                              const float *params_dev, int64_t nsamp, const dfhm_feature_desc *fd,
+                              uint16_t *x_dev, void *stream)
+{
+    if (!wall_dev || !t_dev || !sines_dev || !params_dev || !fd || !x_dev || nsamp < 0)
+        return DFHM_E_INVAL;
+    if (fd->n_hist < 1 || fd->stride < 2 * fd->n_hist + 8 || fd->stride % 8 || !(fd->dt_hist > 0.f))
+        return DFHM_E_INVAL;
+    if (nsamp == 0) return DFHM_OK;
+    FeatDesc d;
+    d.n_hist = fd->n_hist;
+    d.stride = fd->stride;
+    d.dt_hist = fd->dt_hist;
+    d.T_mean = fd->T_mean; d.T_scale = fd->T_scale;
+    d.RH_mean = fd->RH_mean; d.RH_scale = fd->RH_scale;
+    for (int i = 0; i < 8; ++i) { d.p_mean[i] = fd->p_mean[i]; d.p_scale[i] = fd->p_scale[i]; }
+    hipLaunchKernelGGL(k_features, dim3((unsigned)nsamp), dim3(256), 0, (hipStream_t)stream, wall_dev,
+                       t_dev, sines_dev, params_dev, (int)nsamp, d, x_dev);
+    return hipGetLastError() == hipSuccess ? DFHM_OK : DFHM_E_DEVICE;
+}
+
+dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scale, float tau,
+                            float *flux_dev, uint8_t *fallback_dev, void *stream)
+{
+    if (!y_dev || !scale || !flux_dev || !fallback_dev || batch < 0 || !(tau > 0.f))
+        return DFHM_E_INVAL;
+    if (batch == 0) return DFHM_OK;
+    DecodeScale sc;
+    for (int i = 0; i < 4; ++i) {
+        sc.m[i] = scale[2 * i];
+        sc.s[i] = scale[2 * i + 1];
+        if (!std::isfinite(sc.m[i]) || !(sc.s[i] > 0.f) || !std::isfinite(sc.s[i])) return DFHM_E_INVAL;
+    }
+    hipLaunchKernelGGL(k_decode, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, y_dev, batch, sc, tau, flux_dev, fallback_dev);
+    return hipGetLastError() == hipSuccess ? DFHM_OK : DFHM_E_DEVICE;
+}
+
+const char *dfhm_mlp_last_error(const dfhm_mlp *m) { return m ? m->err.c_str() : "null network"; }
+
+void dfhm_mlp_destroy(dfhm_mlp *m)
+{
+    if (!m) return;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    else (void)hipDeviceSynchronize();
+    for (void *p : m->allocs) (void)hipFree(p);
+    delete m;
+}
+
+} // extern "C"

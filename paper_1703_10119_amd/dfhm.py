@@ -74,10 +74,29 @@ class Info(C.Structure):
                 ("step_index", C.c_int64), ("pack_efficiency", C.c_double)]
 
 
+class MlpConfig(C.Structure):
+    """dfhm_mlp_config"""
+    _fields_ = [("n_in", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
+                ("n_out", C.c_int32), ("max_batch", C.c_int32), ("act_pairs", C.c_int32),
+                ("seed", C.c_uint64), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("weight_decay", C.c_float), ("stream", C.c_void_p)]
+
+
+class FeatureDesc(C.Structure):
+    """dfhm_feature_desc"""
+    _fields_ = [("n_hist", C.c_int32), ("stride", C.c_int32), ("dt_hist", C.c_float),
+                ("T_mean", C.c_float), ("T_scale", C.c_float), ("RH_mean", C.c_float),
+                ("RH_scale", C.c_float), ("p_mean", C.c_float * 8), ("p_scale", C.c_float * 8)]
+
+
 EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_step_n", "dfhm_sync",
            "dfhm_fluxes", "dfhm_get_fields", "dfhm_get_all_fields", "dfhm_set_fields",
            "dfhm_set_step_index", "dfhm_get_rooms", "dfhm_get_info", "dfhm_autotune",
-           "dfhm_step_index", "dfhm_last_error", "dfhm_status_string", "dfhm_destroy")
+           "dfhm_step_index", "dfhm_last_error", "dfhm_status_string", "dfhm_destroy",
+           "dfhm_mlp_create", "dfhm_mlp_param_count", "dfhm_mlp_get_params",
+           "dfhm_mlp_set_params", "dfhm_mlp_forward", "dfhm_mlp_gradients",
+           "dfhm_mlp_train_step", "dfhm_mlp_last_error", "dfhm_mlp_destroy",
+           "dfhm_mlp_features", "dfhm_mlp_decode")
 
 _lib = None
 
@@ -117,6 +136,25 @@ def load(path: str = LIB_PATH):
     for f in (L.dfhm_create, L.dfhm_room_couple, L.dfhm_step_n, L.dfhm_sync, L.dfhm_fluxes,
               L.dfhm_get_fields, L.dfhm_get_all_fields, L.dfhm_set_fields,
               L.dfhm_set_step_index, L.dfhm_get_rooms, L.dfhm_get_info, L.dfhm_autotune):
+        f.restype = C.c_int
+    # surface-flux surrogate
+    L.dfhm_mlp_create.argtypes = [C.POINTER(MlpConfig), C.POINTER(P)]
+    L.dfhm_mlp_param_count.restype = I64
+    L.dfhm_mlp_param_count.argtypes = [P]
+    L.dfhm_mlp_get_params.argtypes = [P, P]
+    L.dfhm_mlp_set_params.argtypes = [P, P]
+    L.dfhm_mlp_forward.argtypes = [P, P, I64, P]
+    L.dfhm_mlp_gradients.argtypes = [P, P, P, I64, P, P]
+    L.dfhm_mlp_train_step.argtypes = [P, P, P, I64, C.c_float, P]
+    L.dfhm_mlp_last_error.restype = C.c_char_p
+    L.dfhm_mlp_last_error.argtypes = [P]
+    L.dfhm_mlp_destroy.restype = None
+    L.dfhm_mlp_destroy.argtypes = [P]
+    L.dfhm_mlp_features.argtypes = [P, P, P, P, I64, C.POINTER(FeatureDesc), P, P]
+    L.dfhm_mlp_decode.argtypes = [P, I64, P, C.c_float, P, P, P]
+    for f in (L.dfhm_mlp_create, L.dfhm_mlp_get_params, L.dfhm_mlp_set_params,
+              L.dfhm_mlp_forward, L.dfhm_mlp_gradients, L.dfhm_mlp_train_step,
+              L.dfhm_mlp_features, L.dfhm_mlp_decode):
         f.restype = C.c_int
     _lib = L
     return L

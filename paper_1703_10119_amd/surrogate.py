@@ -1,0 +1,288 @@
+"""Surface-flux surrogate: an MLP trained on histories the DF solver produces.
+
+Not part of the paper.  The network predicts the next 10-min mean interior
+(side 1) surface fluxes of a wall of the identical-grid batch from the 48 h
+outdoor history of its side 0 (T and RH every 10 min), five wall parameters
+and the time; the Dufort-Frankel solve is both the source of the training
+targets and the fallback when the network's own error estimate is too large.
+Every kernel (DF steps, feature rows, GEMMs, loss, AdamW, decode) runs on the
+GPU through the C ABI; this module only orchestrates calls and computes the
+summary statistics.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import math
+import time
+
+import numpy as np
+
+from . import dfhm, workloads as wl
+
+N_HIST = 288          # 48 h at 10-min spacing
+STRIDE = 584          # feature row: 576 history values + 8 parameters
+WINDOW_S = 600.0      # prediction interval
+SPINUP_S = 48 * 3600.0
+N_WINDOWS = 156       # 26 h of windows after the spin-up
+
+
+MlpConfig, FeatureDesc = dfhm.MlpConfig, dfhm.FeatureDesc
+
+
+def _lib():
+    return dfhm.load()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class MLP:
+    """The network on the current device (BF16 MFMA, FP32 master weights)."""
+
+    def __init__(self, n_in=STRIDE, width=512, depth=4, n_out=8, max_batch=65536, seed=0,
+                 beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, act_pairs=False):
+        L = _lib()
+        c = MlpConfig(n_in, width, depth, n_out, max_batch, int(bool(act_pairs)), seed, beta1,
+                      beta2, eps, weight_decay, _stream())
+        h = C.c_void_p()
+        st = L.dfhm_mlp_create(C.byref(c), C.byref(h))
+        if st != 0:
+            raise dfhm.DfhmError(st, "dfhm_mlp_create")
+        self._h = h
+        self.dims = (n_in, width, depth, n_out)
+        self.act_pairs = bool(act_pairs)
+        self.n_params = int(L.dfhm_mlp_param_count(h))
+        self.max_batch = max_batch
+
+    def _check(self, st, what):
+        if st != 0:
+            raise dfhm.DfhmError(st, f"{what}: {_lib().dfhm_mlp_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().dfhm_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, x):
+        import torch
+        B = x.shape[0]
+        y = torch.empty((B, self.dims[3]), dtype=torch.float32, device=x.device)
+        self._check(_lib().dfhm_mlp_forward(self._h, x.data_ptr(), B, y.data_ptr()), "forward")
+        return y
+
+    def train_step(self, x, y, lr, want_loss=False):
+        loss = C.c_float(0.0)
+        self._check(_lib().dfhm_mlp_train_step(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                               float(lr), C.byref(loss) if want_loss else None),
+                    "train_step")
+        return float(loss.value) if want_loss else None
+
+    def gradients(self, x, y):
+        g = np.empty(self.n_params, np.float32)
+        loss = C.c_float(0.0)
+        self._check(_lib().dfhm_mlp_gradients(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                              g.ctypes.data_as(C.c_void_p), C.byref(loss)),
+                    "gradients")
+        return g, float(loss.value)
+
+    def get_params(self):
+        p = np.empty(self.n_params, np.float32)
+        self._check(_lib().dfhm_mlp_get_params(self._h, p.ctypes.data_as(C.c_void_p)), "get")
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self._check(_lib().dfhm_mlp_set_params(self._h, p.ctypes.data_as(C.c_void_p)), "set")
+
+
+def wall_inputs(walls):
+    """Per-wall sinusoids of side 0 [W, 8] and 5 parameters [W, 5]: log10 of
+    the four law scales of layer 0 and the wall thickness."""
+    W = len(walls["nx"])
+    sines = np.concatenate([walls["Tamb"][:, 0, :], walls["RHamb"][:, 0, :]], axis=1)
+    F = wl.LAYER_FIELDS
+    lay = walls["layer"][:, 0, :]
+    params = np.stack([np.log10(lay[:, F.index("k0")]), np.log10(lay[:, F.index("kM0")]),
+                       np.log10(lay[:, F.index("c0")]), np.log10(lay[:, F.index("cM0")]),
+                       walls["layer"][:, :, F.index("thick")].sum(axis=1)], axis=1)
+    return np.ascontiguousarray(sines, np.float64).reshape(W, 8), params.astype(np.float32)
+
+
+def feature_desc(params, t_lo, t_hi):
+    """Normalisation of the feature rows (history around 293 K / RH 0.6;
+    parameter means and spreads of the training walls; time over its range)."""
+    d = FeatureDesc()
+    d.n_hist, d.stride, d.dt_hist = N_HIST, STRIDE, WINDOW_S
+    d.T_mean, d.T_scale, d.RH_mean, d.RH_scale = 293.0, 10.0, 0.6, 0.2
+    mu = params.mean(axis=0)
+    sd = params.std(axis=0)
+    for i in range(5):
+        d.p_mean[i] = float(mu[i])
+        d.p_scale[i] = float(sd[i]) if sd[i] > 1e-6 else 1.0
+    d.p_mean[5] = 0.5 * (t_lo + t_hi) / 86400.0
+    d.p_scale[5] = max(0.5 * (t_hi - t_lo) / 86400.0, 1e-3)
+    for i in (6, 7):
+        d.p_mean[i], d.p_scale[i] = 0.0, 0.7071
+    return d
+
+
+def features(wall_idx, t, sines_d, params_d, desc):
+    """BF16 feature rows (as int16 torch tensor) of samples (wall, time)."""
+    import torch
+    n = int(wall_idx.shape[0])
+    x = torch.empty((n, STRIDE), dtype=torch.int16, device=wall_idx.device)
+    st = _lib().dfhm_mlp_features(wall_idx.data_ptr(), t.data_ptr(), sines_d.data_ptr(),
+                                  params_d.data_ptr(), n, C.byref(desc), x.data_ptr(), _stream())
+    if st != 0:
+        raise dfhm.DfhmError(st, "dfhm_mlp_features")
+    return x
+
+
+def generate(walls, precision=dfhm.FP32, dt=1.0, spinup_s=SPINUP_S, n_windows=N_WINDOWS):
+    """Run the DF solver on a wall batch and return the window targets.
+
+    Returns dict(flux [W, n_windows, 2] side-1 mean (heat W/m2, vapour
+    kg/(m2 s)), t [n_windows] window start times, df_seconds, steps)."""
+    import torch
+    cfg = wl.default_config(dt=dt)
+    s = dfhm.Solver(walls, cfg, precision=precision, schedule=dfhm.SCHED_RESIDENT)
+    spin = int(round(spinup_s / dt))
+    wsteps = int(round(WINDOW_S / dt))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(spin)
+    _, I_prev = s.fluxes()
+    out = np.empty((len(walls["nx"]), n_windows, 2))
+    for k in range(n_windows):
+        s.step(wsteps)
+        _, I = s.fluxes()
+        out[:, k, :] = (I[:, 1, :] - I_prev[:, 1, :]) / (wsteps * dt)
+        I_prev = I
+    s.sync()
+    secs = time.perf_counter() - t0
+    s.close()
+    t_win = spinup_s + WINDOW_S * np.arange(n_windows)
+    return dict(flux=out, t=t_win, df_seconds=secs, steps=spin + n_windows * wsteps)
+
+
+class Targets:
+    """Per-wall scale split of the window fluxes: u = flux / RMS_w and
+    l = log RMS_w per field (RMS over the windows of the wall), each z-scored
+    with the training set's mean and std."""
+
+    def __init__(self, flux):
+        u, l = self.split(flux)
+        self.mean = np.array([u[..., 0].mean(), u[..., 1].mean(), l[..., 0].mean(), l[..., 1].mean()])
+        self.std = np.array([u[..., 0].std(), u[..., 1].std(), l[..., 0].std(), l[..., 1].std()])
+        self.std = np.where(self.std > 0, self.std, 1.0)
+
+    @staticmethod
+    def split(flux):
+        rms = np.sqrt(np.mean(flux ** 2, axis=1, keepdims=True))
+        rms = np.maximum(rms, 1e-300)
+        return flux / rms, np.broadcast_to(np.log(rms), flux.shape)
+
+    def norm(self, flux):
+        """[W, K, 2] fluxes -> [W, K, 4] normalised targets (u_q, u_g, l_q, l_g)."""
+        u, l = self.split(flux)
+        t = np.concatenate([u, l], axis=2)
+        return (t - self.mean) / self.std
+
+    def scale8(self):
+        return np.array([v for i in range(4) for v in (self.mean[i], self.std[i])], np.float32)
+
+
+def train(net, data, walls, desc, targets, epochs=3, batch=8192, lr=1e-3, seed=0, log=None):
+    """AdamW on all (wall, window) samples of `data`; linear warm-up, then a
+    cosine learning-rate decay."""
+    import torch
+    dev = "cuda"
+    sines, params = wall_inputs(walls)
+    sines_d = torch.tensor(sines, device=dev)
+    params_d = torch.tensor(params, device=dev)
+    W, K = data["flux"].shape[:2]
+    y_all = torch.tensor(targets.norm(data["flux"]).reshape(-1, 4), dtype=torch.float32, device=dev)
+    wall_of = torch.arange(W, device=dev, dtype=torch.int32).repeat_interleave(K)
+    t_of = torch.tensor(np.tile(data["t"], W), dtype=torch.float64, device=dev)
+    n = W * K
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    steps = epochs * (n // batch)
+    warm = max(1, steps // 20)              # linear warm-up over the first 5 %
+    k = 0
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g, device=dev)
+        for b in range(n // batch):
+            idx = perm[b * batch:(b + 1) * batch]
+            x = features(wall_of[idx].contiguous(), t_of[idx].contiguous(), sines_d, params_d, desc)
+            y = y_all[idx].contiguous()
+            cur = lr * min(1.0, (k + 1) / warm) * 0.5 * (1.0 + math.cos(math.pi * k / max(steps, 1)))
+            want = (k % 200 == 0) or (k == steps - 1)
+            loss = net.train_step(x, y, cur, want_loss=want)
+            if want:
+                losses.append((k, loss))
+                if log:
+                    log(f"  step {k}/{steps} loss {loss:.4f}")
+            k += 1
+    torch.cuda.synchronize()
+    return dict(losses=losses, seconds=time.perf_counter() - t0, steps=steps, samples=steps * batch)
+
+
+def predict(net, walls, t_windows, desc, targets, tau, batch=65536):
+    """Network fluxes [W, K, 2] and fallback flags [W, K] for all windows."""
+    import torch
+    dev = "cuda"
+    sines, params = wall_inputs(walls)
+    sines_d = torch.tensor(sines, device=dev)
+    params_d = torch.tensor(params, device=dev)
+    W, K = len(walls["nx"]), len(t_windows)
+    wall_of = torch.arange(W, device=dev, dtype=torch.int32).repeat_interleave(K)
+    t_of = torch.tensor(np.tile(t_windows, W), dtype=torch.float64, device=dev)
+    n = W * K
+    flux = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    fb = torch.empty(n, dtype=torch.uint8, device=dev)
+    sc = np.ascontiguousarray(targets.scale8())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b0 in range(0, n, batch):
+        b1 = min(n, b0 + batch)
+        x = features(wall_of[b0:b1].contiguous(), t_of[b0:b1].contiguous(), sines_d, params_d, desc)
+        y = net.forward(x)
+        st = _lib().dfhm_mlp_decode(y.data_ptr(), b1 - b0, sc.ctypes.data_as(C.c_void_p),
+                                    float(tau), flux[b0:].data_ptr(), fb[b0:].data_ptr(), _stream())
+        if st != 0:
+            raise dfhm.DfhmError(st, "dfhm_mlp_decode")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    return (flux.cpu().numpy().reshape(W, K, 2).astype(np.float64),
+            fb.cpu().numpy().reshape(W, K).astype(bool), secs)
+
+
+def errors(pred, truth):
+    """|pred - truth| / RMS over the windows of the truth, per wall and field."""
+    rms = np.sqrt(np.mean(truth ** 2, axis=1, keepdims=True))
+    return np.abs(pred - truth) / rms
+
+
+def calibrate_tau(net, walls, data, desc, targets, target=0.01, q=0.99):
+    """Largest fallback threshold (predicted relative error) whose p-q error
+    after fallback is <= target on the given (calibration) walls."""
+    for tau in np.geomspace(0.1, 0.0005, 40):
+        pred, fb, _ = predict(net, walls, data["t"], desc, targets, tau)
+        e = errors(pred, data["flux"]).max(axis=2)
+        e[fb] = 0.0                      # fallback samples are the DF solve itself
+        if np.quantile(e, q) <= target:
+            return float(tau)
+    return None
