@@ -171,7 +171,9 @@ def generate(walls, precision=dfhm.FP32, dt=1.0, spinup_s=SPINUP_S, n_windows=N_
     secs = time.perf_counter() - t0
     s.close()
     t_win = spinup_s + WINDOW_S * np.arange(n_windows)
-    return dict(flux=out, t=t_win, df_seconds=secs, steps=spin + n_windows * wsteps)
+    steps = spin + n_windows * wsteps
+    return dict(flux=out, t=t_win, df_seconds=secs, steps=steps,
+                cell_updates=float(wl.total_nodes(walls)) * steps, window_steps=wsteps)
 
 
 class Targets:
@@ -286,3 +288,65 @@ def calibrate_tau(net, walls, data, desc, targets, target=0.01, q=0.99):
         if np.quantile(e, q) <= target:
             return float(tau)
     return None
+
+
+def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=16384,
+          target=0.01, q=0.99, cal_margin=0.9, seed=1, act_pairs=False, log=None):
+    """Train on DF histories, calibrate the fallback threshold on one set of
+    walls and measure error and speed-up on another (all C2-type walls:
+    30 cm, 1001 nodes, dt = 1 s, different generator seeds).
+
+    Error: |q_MLP - q_DF| / RMS over the windows of q_DF, per wall and
+    field; a sample's error is the larger of its two fields, and fallback
+    samples take the DF value (error 0).  tau is the largest threshold whose
+    q-quantile error on the calibration walls is <= cal_margin * target.
+    Speed-up = DF time / (MLP time + DF time of the fallback samples), with
+    the DF cost of one sample taken at the measured batched DF throughput:
+      warm: 600 steps (the DF state is carried from the previous window),
+      cold: 48 h + 10 min of steps (the state is rebuilt from scratch)."""
+    import torch
+    say = log or (lambda *a: None)
+    tr = wl.uniform_batch(n_train, seed=505)
+    ca = wl.uniform_batch(n_cal, seed=515)
+    te = wl.uniform_batch(n_test, seed=516)
+    d_tr = generate(tr)
+    say(f"DF data: {n_train} walls x {d_tr['steps']} steps in {d_tr['df_seconds']:.1f} s")
+    d_ca = generate(ca)
+    d_te = generate(te)
+    targets = Targets(d_tr["flux"])
+    _, params = wall_inputs(tr)
+    desc = feature_desc(params, d_tr["t"][0], d_tr["t"][-1])
+    net = MLP(max_batch=65536, seed=seed, act_pairs=act_pairs)
+    fit = train(net, d_tr, tr, desc, targets, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
+    say(f"trained {fit['steps']} steps of {batch} in {fit['seconds']:.1f} s")
+    tau = calibrate_tau(net, ca, d_ca, desc, targets, target=cal_margin * target, q=q)
+    predict(net, te, d_te["t"], desc, targets, 10.0)            # warm-up
+    pred, fb, mlp_s = predict(net, te, d_te["t"], desc, targets, tau if tau else 1e-30)
+    e_raw = errors(pred, d_te["flux"]).max(axis=2)
+    e = e_raw.copy()
+    e[fb] = 0.0
+    n_samp = e.size
+    f = float(fb.mean())
+    # DF cost per sample at the measured throughput of the held-out run
+    per_update = d_te["df_seconds"] / d_te["cell_updates"]
+    nodes = float(wl.total_nodes(te)) / n_test
+    warm_sample = per_update * nodes * d_te["window_steps"]
+    cold_steps = int(round((SPINUP_S + WINDOW_S) / 1.0))
+    cold_sample = per_update * nodes * cold_steps
+    df_warm = n_samp * warm_sample
+    df_cold = n_samp * cold_sample
+    flops = 2.0 * net.n_params * n_samp          # multiply-adds of the forward pass
+    net.close()
+    return dict(
+        tau=tau, fallback_fraction=f, samples=n_samp,
+        err_p50=float(np.median(e)), err_p99=float(np.quantile(e, q)), err_max=float(e.max()),
+        raw_err_p50=float(np.median(e_raw)), raw_err_p99=float(np.quantile(e_raw, q)),
+        mlp_seconds=mlp_s, mlp_tflops=flops / mlp_s / 1e12,
+        df_warm_seconds=df_warm, df_cold_seconds=df_cold,
+        speedup_warm=df_warm / (mlp_s + f * df_warm),
+        speedup_cold=df_cold / (mlp_s + f * df_cold),
+        speedup_no_fallback_warm=df_warm / mlp_s,
+        train_seconds=fit["seconds"], train_samples=fit["samples"],
+        train_tflops=3.0 * 2.0 * net.n_params * fit["samples"] / fit["seconds"] / 1e12,
+        data_seconds=d_tr["df_seconds"], n_train=n_train, n_cal=n_cal, n_test=n_test,
+        epochs=epochs, batch=batch, lr=lr)
