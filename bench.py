@@ -48,11 +48,17 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--schedule", default="resident", choices=["auto", "stream", "resident"])
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--walls", type=int, default=N_WALLS)
+    ap.add_argument("--workload", default="identical", choices=["identical", "layered", "building"],
+                    help="identical: the 65,536 x 1001 batch (the default and the headline); "
+                         "layered: 100,000 uneven 1-3 layer walls (FP32, dt = 1 s); "
+                         "building: 4,096 rooms x 6 walls coupled to the room-air balance")
+    ap.add_argument("--rooms", type=int, default=4096)
+    ap.add_argument("--dt", type=float, default=None)
     ap.add_argument("--cpu-walls", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=10000)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
@@ -63,11 +69,11 @@ def parse():
     return ap.parse_args()
 
 
-def run_gpu(dfhm, walls, cfg, prec, schedule, steps, warmup):
+def run_gpu(dfhm, walls, cfg, prec, schedule, steps, warmup, rooms=None):
     import torch
     sched = {"auto": dfhm.SCHED_AUTO, "stream": dfhm.SCHED_STREAM,
              "resident": dfhm.SCHED_RESIDENT}[schedule]
-    s = dfhm.Solver(walls, cfg, precision=prec, schedule=sched)
+    s = dfhm.Solver(walls, cfg, rooms=rooms, precision=prec, schedule=sched)
     if schedule == "auto":
         s.autotune(probe_steps=50)
     s.step(warmup)
@@ -89,14 +95,43 @@ def run_gpu(dfhm, walls, cfg, prec, schedule, steps, warmup):
     return ms, info, finite
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "counters_k_df_resident_65536x1001.md")
+KERNEL_SOURCES = ("df_resident.hpp", "df_kernels.hpp", "dfhm_device.hpp")
+
+
+def resident_traffic(dtype):
+    """HBM bytes per launch of the resident kernel from the committed FETCH_SIZE
+    / WRITE_SIZE counters (scaled by a plain copy's readings), or None when
+    the kernel sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read().split("```")
+        block = text[-2] if len(text) >= 3 else ""        # the last fenced block
+        kv = dict((k.strip(), v.strip()) for k, v in
+                  (ln.split(":", 1) for ln in block.splitlines() if ":" in ln))
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(ROOT, "paper_1703_10119_amd", "csrc", f), "rb").read())
+        if kv.get("kernel_sources_sha256") != h.hexdigest():
+            return None
+        gib = float(kv["copy.bytes"]) / 1024.0
+        fetch = float(kv[f"{dtype}.fetch_kib"]) * gib / float(kv["copy.fetch_kib"])
+        write = float(kv[f"{dtype}.write_kib"]) * gib / float(kv["copy.write_kib"])
+        return round((fetch + write) * 1024.0)
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline(dtype, cells, steps, ms, info):
     if info["schedule"] == 2:   # resident: VALU-bound, one launch per chunk
         launches = math.ceil(steps / info["chunk_steps"])
         per_launch_s = ms / 1e3 / launches
         flops = FLOPS_PER_CELL * cells * steps / launches
         ach = flops / per_launch_s / 1e12
+        chunk_full = steps % info["chunk_steps"] == 0 and info["chunk_steps"] == 1000
         return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK[dtype],
-                "unit": "TFLOP/s", "frac": round(ach / PEAK[dtype], 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK[dtype], 4),
+                "traffic": resident_traffic(dtype) if chunk_full and cells == 65536 * NX else None,
                 "kernel": "k_df_resident", "launch_ms": round(per_launch_s * 1e3, 3)}
     per_launch_s = ms / 1e3 / steps
     ach = BYTES_PER_CELL[dtype] * cells / per_launch_s / 1e9
@@ -121,6 +156,38 @@ def cpu_baseline(walls_fn, cfg, n_walls, steps):
                       f"(FP64 C oracle, OpenMP over walls), {dt:.1f} s"}
 
 
+def other_workload(a, torch, dfhm, wl):
+    """The uneven layered batch or the building batch: cell-updates/s of the
+    resident (or chosen) schedule in FP32 and FP64."""
+    rooms = None
+    if a.workload == "layered":
+        dt = a.dt or 1.0
+        walls = wl.layered_batch(100000 if a.walls == N_WALLS else a.walls, seed=303, dt=dt)
+        name = (f"uneven batch: {len(walls['nx'])} walls, 1-3 layers, lognormal Nx (median 300, "
+                f"capped at dt/dx <= 3333 s/m), dt = {dt:g} s")
+    else:
+        dt = a.dt or 10.0
+        walls, rooms = wl.building_batch(a.rooms, seed=404, dt=dt)
+        name = (f"building batch: {a.rooms} rooms x 6 layered walls (Nx 101-801, capped), "
+                f"room-air balance every step, dt = {dt:g} s")
+    cfg = wl.default_config(dt=dt)
+    cells = int(wl.total_nodes(walls))
+    out = {"metric": "DF cell-updates/s", "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": name, "walls": len(walls["nx"]), "cells": cells, "dt_s": dt,
+                      "rooms": 0 if rooms is None else len(rooms["volume"])}}
+    for key, prec, dtype in (("fp32", dfhm.FP32, "f32"), ("fp64", dfhm.FP64, "f64")):
+        if a.precision not in ("both", key):
+            continue
+        ms, info, fin = run_gpu(dfhm, walls, cfg, prec, a.schedule, a.steps, a.warmup, rooms)
+        out[key] = {"value": cells * a.steps / (ms / 1e3), "ms_per_step": ms / a.steps,
+                    "roofline": roofline(dtype, cells, a.steps, ms, info), "finite": fin,
+                    "schedule": ["", "stream", "resident"][info["schedule"]],
+                    "block_threads": info["block_threads"],
+                    "nodes_per_thread": info["nodes_per_thread"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -138,6 +205,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.workload != "identical":
+        other_workload(a, torch, dfhm, wl)
+        return
     cfg = wl.default_config(dt=DT)
     walls = wl.uniform_batch(a.walls, seed=202, nx=NX)
     cells = a.walls * NX
@@ -171,7 +241,14 @@ def main():
     if not a.no_surrogate:
         from paper_1703_10119_amd import surrogate as S
         r = S.study(epochs=a.surrogate_epochs)
+        kb = S.kernel_bench()
         out["surrogate"] = {
+            "roofline": {"bound": "mfma", "achieved": round(kb["forward_tflops"], 2),
+                         "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": round(kb["forward_tflops"] / 2500.0, 4), "traffic": None,
+                         "kernel": "k_gemm_bf16 (forward pass, batch 65,536)",
+                         "forward_ms": round(kb["forward_s"] * 1e3, 4),
+                         "train_step_tflops": round(kb["train_tflops"], 2)},
             "speedup_warm": r["speedup_warm"], "speedup_cold": r["speedup_cold"],
             "err_target": "p99 <= 1% of the per-wall RMS flux, after fallback",
             "err_p50": r["err_p50"], "err_p99": r["err_p99"], "err_max": r["err_max"],
@@ -180,8 +257,7 @@ def main():
             "speedup_no_fallback_warm": r["speedup_no_fallback_warm"],
             "test_samples": r["samples"], "mlp_seconds": r["mlp_seconds"],
             "df_warm_seconds": r["df_warm_seconds"], "df_cold_seconds": r["df_cold_seconds"],
-            "inference_tflops": r["mlp_tflops"], "train_tflops": r["train_tflops"],
-            "mfma_peak_bf16_tflops": 2500.0,
+            "inference_tflops_end_to_end": r["mlp_tflops"], "train_tflops_end_to_end": r["train_tflops"],
             "train": {"walls": r["n_train"], "samples_per_epoch": r["n_train"] * S.N_WINDOWS,
                       "epochs": r["epochs"], "batch": r["batch"], "lr": r["lr"],
                       "seconds": r["train_seconds"], "data_seconds": r["data_seconds"]},

@@ -350,3 +350,53 @@ def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=1638
         train_tflops=3.0 * 2.0 * net.n_params * fit["samples"] / fit["seconds"] / 1e12,
         data_seconds=d_tr["df_seconds"], n_train=n_train, n_cal=n_cal, n_test=n_test,
         epochs=epochs, batch=batch, lr=lr)
+
+
+def kernel_bench(batch=65536, train_batch=16384, iters=50, act_pairs=False, seed=0):
+    """Time the network's kernels alone on synthetic BF16 inputs: forward at
+    the inference batch and one AdamW training step, with HIP events on the
+    stream the kernels are launched on.  FLOPs are the GEMMs' multiply-adds
+    (2 per weight per sample; x3 for a training step)."""
+    import torch
+    dev = "cuda"
+    net = MLP(max_batch=max(batch, train_batch), seed=seed, act_pairs=act_pairs)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    x = (torch.randn((batch, STRIDE), generator=g, device=dev)
+         .to(torch.bfloat16).view(torch.int16).contiguous())
+    xt = x[:train_batch].contiguous()
+    yt = torch.randn((train_batch, 4), generator=g, device=dev)
+    stream = torch.cuda.current_stream()
+    n_w = net.n_params - sum(net.dims[1] for _ in range(net.dims[2])) - net.dims[3]
+    mult = 2.0 if act_pairs else 1.0          # pairs double every GEMM after the first
+    k_first = net.dims[0] * net.dims[1]
+    fwd_flops = 2.0 * (k_first + mult * (n_w - k_first))
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / n
+
+    t_fwd = timed(lambda: net.forward(x), iters)
+    t_train = timed(lambda: net.train_step(xt, yt, 1e-4), iters)
+    net.close()
+    return dict(forward_s=t_fwd, forward_tflops=fwd_flops * batch / t_fwd / 1e12,
+                train_step_s=t_train,
+                train_tflops=3.0 * fwd_flops * train_batch / t_train / 1e12,
+                batch=batch, train_batch=train_batch, flops_per_sample=fwd_flops)
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="surrogate kernel timing")
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--pairs", action="store_true")
+    a = ap.parse_args()
+    print(json.dumps(kernel_bench(iters=a.iters, act_pairs=a.pairs)), flush=True)
