@@ -58,6 +58,8 @@ def parse():
                          "layered: 100,000 uneven 1-3 layer walls (FP32, dt = 1 s); "
                          "building: 4,096 rooms x 6 walls coupled to the room-air balance")
     ap.add_argument("--rooms", type=int, default=4096)
+    ap.add_argument("--shape", default=None,
+                    help="resident launch shape THREADSxNODES (e.g. 256x4); default: the library's")
     ap.add_argument("--dt", type=float, default=None)
     ap.add_argument("--cpu-walls", type=int, default=1024)
     ap.add_argument("--cpu-steps", type=int, default=10000)
@@ -69,11 +71,15 @@ def parse():
     return ap.parse_args()
 
 
+SHAPE = (0, 0)
+
+
 def run_gpu(dfhm, walls, cfg, prec, schedule, steps, warmup, rooms=None):
     import torch
     sched = {"auto": dfhm.SCHED_AUTO, "stream": dfhm.SCHED_STREAM,
              "resident": dfhm.SCHED_RESIDENT}[schedule]
-    s = dfhm.Solver(walls, cfg, rooms=rooms, precision=prec, schedule=sched)
+    s = dfhm.Solver(walls, cfg, rooms=rooms, precision=prec, schedule=sched,
+                    threads=SHAPE[0], npt=SHAPE[1])
     if schedule == "auto":
         s.autotune(probe_steps=50)
     s.step(warmup)
@@ -190,6 +196,9 @@ def other_workload(a, torch, dfhm, wl):
 
 def main():
     a = parse()
+    global SHAPE
+    if a.shape:
+        SHAPE = tuple(int(v) for v in a.shape.lower().split("x"))
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the batch shards by "
               "walls with no per-step communication, see the design notes", file=sys.stderr)

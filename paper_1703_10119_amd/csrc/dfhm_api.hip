@@ -53,7 +53,7 @@ struct dfhm_ctx {
     ResBlock *d_blocks = nullptr;
     int32_t *d_block_walls = nullptr;
     int32_t *d_block_rooms = nullptr;
-    int n_blocks = 0, max_wpb = 0;
+    int n_blocks = 0, max_wpb = 0, max_rpb = 0;
     double pack_eff = 0.0;
     int res_threads = 0, res_npt = 0;
     bool packed = false;
@@ -397,7 +397,7 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
     }
     std::vector<ResBlock> blocks(bins.size());
     std::vector<int32_t> bw, br;
-    int maxw = 0;
+    int maxw = 0, maxr = 0;
     for (size_t i = 0; i < bins.size(); ++i) {
         std::vector<int32_t> ws;
         std::vector<int32_t> rs;
@@ -418,6 +418,7 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
         B.n_nodes = bins[i].used;
         B.pad = 0;
         maxw = std::max(maxw, (int)ws.size());
+        maxr = std::max(maxr, (int)rs.size());
     }
     if (br.empty()) br.push_back(0);
     size_t o = 0;
@@ -438,6 +439,7 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->n_blocks = (int)blocks.size();
     c->max_wpb = maxw;
+    c->max_rpb = maxr;
     c->pack_eff = (double)c->N / ((double)blocks.size() * cap);
     c->res_threads = nt;
     c->res_npt = npt;
@@ -491,18 +493,22 @@ dfhm_status ensure_packing(dfhm_ctx *c)
 template <typename R, int NPT, int NT>
 void launch_res(dfhm_ctx *c, int k)
 {
-    static bool attr_set = false;   // large shapes need more than 64 KB of LDS
+    static bool attr_set = false;   // the largest tables need more than 64 KB of LDS
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)res_dyn_lds<R>(NT));
+                                  (int)res_lds<R>(NT, kResMaxWalls, kResMaxRooms).total);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_df_resident<R, NPT, NT>), dim3(c->n_blocks), dim3(NT), res_dyn_lds<R>(NT),
-                       c->stream, c->d_blocks, c->d_block_walls, c->d_block_rooms, c->d_walls,
-                       (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0], (R *)c->d_P[1], c->d_lay,
-                       c->d_rooms, c->d_roomT, c->d_roomP, c->d_go, c->d_qh, c->d_flux, c->d_bad,
-                       c->d_step, k, c->rc, c->shape);
+    // LDS tables sized by the largest wall / zone count of a workgroup of
+    // this packing (at least one of each)
+    const int mw = std::max(1, c->max_wpb), mr = std::max(1, c->max_rpb);
+    hipLaunchKernelGGL((k_df_resident<R, NPT, NT>), dim3(c->n_blocks), dim3(NT),
+                       res_lds<R>(NT, mw, mr).total, c->stream, c->d_blocks, c->d_block_walls,
+                       c->d_block_rooms, c->d_walls, (R *)c->d_T[0], (R *)c->d_T[1],
+                       (R *)c->d_P[0], (R *)c->d_P[1], c->d_lay, c->d_rooms, c->d_roomT,
+                       c->d_roomP, c->d_go, c->d_qh, c->d_flux, c->d_bad, c->d_step, k, mw, mr,
+                       c->rc, c->shape);
 }
 
 template <typename R>
