@@ -272,6 +272,22 @@ dfhm_status dfhm_mlp_features(const int32_t *wall_dev, const double *t_dev, cons
 dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scale, float tau,
                             float *flux_dev, uint8_t *fallback_dev, void *stream);
 
+/* Checkpoint / restart.  dfhm_save writes the evolving state of a context —
+ * its step index, both levels of every wall in the storage format (FP64
+ * values, or the FP32 deviations), the flux state (applied fluxes, Neumaier
+ * sums and compensations) and the zone air — into a host buffer after a
+ * header (magic, version, precision, wall / node / zone counts and a digest of
+ * the wall and zone descriptors).  With buf == NULL it only stores the
+ * required size in *bytes; otherwise *bytes must hold at least that size
+ * (DFHM_E_INVAL) and receives the size written.  dfhm_load restores such a
+ * buffer into a context created from the same walls, zones and precision
+ * (DFHM_E_INVAL otherwise, state unchanged), which then continues exactly as
+ * the saving context would have: the DF recurrence only needs levels n and
+ * n-1 (eq. dufort), and the ambient and zone schedules are functions of the
+ * step index.  Both synchronise the context's stream; the caller owns buf. */
+dfhm_status dfhm_save(dfhm_ctx *ctx, void *buf, size_t *bytes);
+dfhm_status dfhm_load(dfhm_ctx *ctx, const void *buf, size_t bytes);
+
 int64_t dfhm_step_index(const dfhm_ctx *ctx);
 const char *dfhm_last_error(const dfhm_ctx *ctx);
 const char *dfhm_status_string(dfhm_status s);

@@ -981,6 +981,121 @@ dfhm_status dfhm_get_info(const dfhm_ctx *c, dfhm_info *info)
     return DFHM_OK;
 }
 
+// ------------------------------------------------------------ checkpoints
+
+namespace {
+constexpr uint64_t kCkptMagic = 0x31504b434d484644ull;   // "DFHMCKP1"
+
+struct CkptHeader {
+    uint64_t magic;
+    int32_t version, precision;
+    int64_t n_walls, n_nodes, n_rooms, step;
+    uint64_t digest;                 // of the wall and zone descriptors
+    uint64_t payload;                // bytes after the header
+};
+
+// FNV-1a over the walls' and zones' defining fields (host copies)
+uint64_t describe(const dfhm_ctx *c)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    };
+    for (const WallDev &W : c->walls) {
+        mix(&W.nx, sizeof W.nx);
+        mix(&W.n_layers, sizeof W.n_layers);
+        mix(W.lay, sizeof W.lay);
+        mix(W.hT, sizeof W.hT);
+        mix(W.hM, sizeof W.hM);
+        mix(&W.T0, sizeof W.T0);
+        mix(&W.RH0, sizeof W.RH0);
+    }
+    mix(c->wall_room.data(), sizeof(int64_t) * c->wall_room.size());
+    mix(&c->nr, sizeof c->nr);
+    return h;
+}
+
+size_t ckpt_payload(const dfhm_ctx *c)
+{
+    return 4 * c->esize * (size_t)c->N + sizeof(double) * (12 * (size_t)c->nw + 2 * (size_t)c->nr);
+}
+} // namespace
+
+dfhm_status dfhm_save(dfhm_ctx *c, void *buf, size_t *bytes)
+{
+    if (!c || !bytes) return DFHM_E_INVAL;
+    const size_t need = sizeof(CkptHeader) + ckpt_payload(c);
+    if (!buf) { *bytes = need; return DFHM_OK; }
+    if (*bytes < need) return fail(c, DFHM_E_INVAL, "checkpoint buffer too small");
+    CkptHeader h{};
+    h.magic = kCkptMagic;
+    h.version = 1;
+    h.precision = c->precision;
+    h.n_walls = c->nw;
+    h.n_nodes = c->N;
+    h.n_rooms = c->nr;
+    h.step = c->n;
+    h.digest = describe(c);
+    h.payload = ckpt_payload(c);
+    char *o = (char *)buf;
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    // level n then level n-1, each T then P, in the storage format
+    const size_t lv = c->esize * (size_t)c->N;
+    for (int level = 0; level < 2; ++level) {
+        const int b = (int)((c->n + level) & 1);
+        HIP_TRY(c, hipMemcpyAsync(o, c->d_T[b], lv, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(o + lv, c->d_P[b], lv, hipMemcpyDeviceToHost, c->stream));
+        o += 2 * lv;
+    }
+    HIP_TRY(c, hipMemcpyAsync(o, c->d_flux, sizeof(double) * 12 * c->nw, hipMemcpyDeviceToHost, c->stream));
+    o += sizeof(double) * 12 * c->nw;
+    if (c->nr) {
+        HIP_TRY(c, hipMemcpyAsync(o, c->d_roomT, sizeof(double) * c->nr, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(o + sizeof(double) * c->nr, c->d_roomP, sizeof(double) * c->nr,
+                                  hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *bytes = need;
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_load(dfhm_ctx *c, const void *buf, size_t bytes)
+{
+    if (!c || !buf) return DFHM_E_INVAL;
+    CkptHeader h;
+    if (bytes < sizeof h) return fail(c, DFHM_E_INVAL, "checkpoint too short");
+    std::memcpy(&h, buf, sizeof h);
+    if (h.magic != kCkptMagic || h.version != 1) return fail(c, DFHM_E_INVAL, "not a dfhm checkpoint");
+    if (h.precision != c->precision || h.n_walls != c->nw || h.n_nodes != c->N || h.n_rooms != c->nr ||
+        h.digest != describe(c) || h.payload != ckpt_payload(c) || bytes < sizeof h + h.payload)
+        return fail(c, DFHM_E_INVAL, "checkpoint of different walls, zones or precision");
+    if (h.step < 0) return fail(c, DFHM_E_INVAL, "negative step index in checkpoint");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfhm_status st = dfhm_set_step_index(c, h.step);
+    if (st) return st;
+    const char *o = (const char *)buf + sizeof h;
+    const size_t lv = c->esize * (size_t)c->N;
+    for (int level = 0; level < 2; ++level) {
+        const int b = (int)((c->n + level) & 1);
+        HIP_TRY(c, hipMemcpy(c->d_T[b], o, lv, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_P[b], o + lv, lv, hipMemcpyHostToDevice));
+        o += 2 * lv;
+    }
+    HIP_TRY(c, hipMemcpy(c->d_flux, o, sizeof(double) * 12 * c->nw, hipMemcpyHostToDevice));
+    o += sizeof(double) * 12 * c->nw;
+    if (c->nr) {
+        HIP_TRY(c, hipMemcpy(c->d_roomT, o, sizeof(double) * c->nr, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_roomP, o + sizeof(double) * c->nr, sizeof(double) * c->nr,
+                             hipMemcpyHostToDevice));
+    }
+    int zero = 0;
+    HIP_TRY(c, hipMemcpy(c->d_bad, &zero, sizeof(int), hipMemcpyHostToDevice));
+    c->latched = DFHM_OK;
+    return DFHM_OK;
+}
+
 int64_t dfhm_step_index(const dfhm_ctx *c) { return c ? c->n : -1; }
 
 const char *dfhm_last_error(const dfhm_ctx *c) { return c ? c->err.c_str() : "null context"; }

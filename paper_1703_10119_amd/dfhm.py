@@ -93,6 +93,7 @@ EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_step_n",
            "dfhm_fluxes", "dfhm_get_fields", "dfhm_get_all_fields", "dfhm_set_fields",
            "dfhm_set_step_index", "dfhm_get_rooms", "dfhm_get_info", "dfhm_autotune",
            "dfhm_step_index", "dfhm_last_error", "dfhm_status_string", "dfhm_destroy",
+           "dfhm_save", "dfhm_load",
            "dfhm_mlp_create", "dfhm_mlp_param_count", "dfhm_mlp_get_params",
            "dfhm_mlp_set_params", "dfhm_mlp_forward", "dfhm_mlp_gradients",
            "dfhm_mlp_train_step", "dfhm_mlp_last_error", "dfhm_mlp_destroy",
@@ -137,6 +138,10 @@ def load(path: str = LIB_PATH):
               L.dfhm_get_fields, L.dfhm_get_all_fields, L.dfhm_set_fields,
               L.dfhm_set_step_index, L.dfhm_get_rooms, L.dfhm_get_info, L.dfhm_autotune):
         f.restype = C.c_int
+    L.dfhm_save.argtypes = [P, P, C.POINTER(C.c_size_t)]
+    L.dfhm_load.argtypes = [P, P, C.c_size_t]
+    L.dfhm_save.restype = C.c_int
+    L.dfhm_load.restype = C.c_int
     # surface-flux surrogate
     L.dfhm_mlp_create.argtypes = [C.POINTER(MlpConfig), C.POINTER(P)]
     L.dfhm_mlp_param_count.restype = I64
@@ -368,6 +373,20 @@ class Solver:
         inf = Info()
         self._check(load().dfhm_get_info(self._h, C.byref(inf)), "dfhm_get_info")
         return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def save(self) -> bytes:
+        """Checkpoint of the evolving state (dfhm_save)."""
+        L = load()
+        n = C.c_size_t(0)
+        self._check(L.dfhm_save(self._h, None, C.byref(n)), "dfhm_save")
+        buf = C.create_string_buffer(n.value)
+        self._check(L.dfhm_save(self._h, buf, C.byref(n)), "dfhm_save")
+        return buf.raw[:n.value]
+
+    def load(self, ckpt: bytes):
+        """Restore a checkpoint written by a context of the same walls (dfhm_load)."""
+        buf = C.create_string_buffer(ckpt, len(ckpt))
+        self._check(load().dfhm_load(self._h, buf, len(ckpt)), "dfhm_load")
 
     def autotune(self, probe_steps: int = 50):
         self._check(load().dfhm_autotune(self._h, int(probe_steps)), "dfhm_autotune")
