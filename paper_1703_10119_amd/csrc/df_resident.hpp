@@ -58,97 +58,106 @@ struct Shape {
 // right face: wall end or padding).
 constexpr int kFaceNone = 6;
 
-// Dynamic LDS layout of one workgroup for nt lanes, mw walls and mr zones.
-struct ResLds {
-    size_t halo, face, flux, surf, amb, rot, bc, room, cc, fk, wstart, wid, wroom, wside, rid, total;
+// One wall's record in LDS (fixed stride, so that every field sits at a
+// compile-time offset from the record base).
+template <typename R> struct WallRec {
+    double flux[12];          // now q, g per side; Neumaier sums; compensations
+    double surf[2][2][2];     // [parity][side][T, P] surface values of level n
+    double amb[2][2][2];      // [parity][side][T, P] ambient at t^n
+    double rot[2][12];        // per side: T mean, amp, RH mean, amp, phase sin/cos, step sin/cos
+    double bc[2][8];          // per side: dx (s / r), h_T, h_M, L_v h_M, g_inf, q_inf, T ref, area
+    R cc[4][4];               // per layer: c0 / r, cM0 / r, theta ref, Pv ref
+    R fk[8][4];               // per entry: k0, kM0 (layer, interface with the next, none),
+                              // theta ref, Pv ref
+    int32_t wstart, wend, wid, wroom, wside, pad[3];
 };
-template <typename R>
-__host__ __device__ constexpr ResLds res_lds(int nt, int mw, int mr)
+struct RoomRec {
+    double air[2][2];         // [parity][T, P]
+    int32_t rid, pad[3];
+};
+// Pointers the kernel needs only after its step loop (read from device
+// memory there, so that they do not occupy scalar registers through the loop).
+struct ResIO {
+    void *T[2], *P[2];
+    const WallDev *walls;
+    double *flux, *roomT, *roomP;
+    int *bad;
+};
+
+// Dynamic LDS layout of one workgroup for nt lanes, mw walls and mr zones:
+// halos and faces need one buffer each (a step's reads of them end before the
+// barrier that precedes their next write).
+template <typename R> __host__ __device__ constexpr size_t res_off_rc(int nt)
 {
-    ResLds o{};
-    size_t p = 0;
-    // halos and faces need one buffer each: a step's reads of them end
-    // before the barrier that precedes their next write
-    o.halo = p;  p += sizeof(R) * 4 * (size_t)nt;          // [4][nt]
-    o.face = p;  p += sizeof(R) * 2 * (size_t)nt;          // [2][nt] kT, kM
-    p = (p + 15) & ~(size_t)15;
-    o.flux = p;  p += sizeof(double) * 12 * (size_t)mw;    // [mw][12]
-    o.surf = p;  p += sizeof(double) * 8 * (size_t)mw;     // [2][mw][2][2]
-    o.amb = p;   p += sizeof(double) * 8 * (size_t)mw;     // [2][mw][2][2]
-    o.rot = p;   p += sizeof(double) * 24 * (size_t)mw;    // [mw][2][12]
-    o.bc = p;    p += sizeof(double) * 16 * (size_t)mw;    // [mw][2][8]
-    o.room = p;  p += sizeof(double) * 4 * (size_t)mr;     // [2][mr][2]
-    p = (p + 15) & ~(size_t)15;
-    o.cc = p;    p += sizeof(R) * 6 * (size_t)mw;          // [mw][3][2]
-    p = (p + 15) & ~(size_t)15;
-    o.fk = p;    p += sizeof(R) * 16 * (size_t)mw;         // [mw][8][2]
-    o.wstart = p; p += sizeof(int32_t) * ((size_t)mw + 1);
-    o.wid = p;   p += sizeof(int32_t) * (size_t)mw;
-    o.wroom = p; p += sizeof(int32_t) * (size_t)mw;
-    o.wside = p; p += sizeof(int32_t) * (size_t)mw;
-    o.rid = p;   p += sizeof(int32_t) * (size_t)mr;
-    o.total = (p + 15) & ~(size_t)15;
-    return o;
+    return ((sizeof(R) * 6 * (size_t)nt) + 15) & ~(size_t)15;
+}
+template <typename R> __host__ __device__ constexpr size_t res_off_walls(int nt)
+{
+    return res_off_rc<R>(nt) + 64;
+}
+template <typename R> __host__ __device__ constexpr size_t res_lds_bytes(int nt, int mw, int mr)
+{
+    return res_off_walls<R>(nt) + sizeof(WallRec<R>) * (size_t)mw + sizeof(RoomRec) * (size_t)mr;
 }
 
 // Keeps the scheduler from interleaving the nodes of a lane (bounds the
 // live registers per lane so that more waves fit).
-#ifndef SCHED_FENCE
 #define SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
-#endif
 
-// Two values of a scale pair from LDS (one 16- or 8-byte read).
-template <typename R> struct Pair { R a, b; };
+// A scale pair and the node's storage references from LDS: FP64 stores
+// absolute values (references are the constants -273.15 K and 0 Pa) and
+// reads the pair (16 B); FP32 stores deviations from the wall's initial state
+// and reads the pair with the wall's references (16 B).
+template <typename R> struct Quad { R a, b, th, p; };
 template <typename R>
-__device__ __forceinline__ Pair<R> lds_pair(const unsigned char *base, int off)
+__device__ __forceinline__ Quad<R> lds_scales(const unsigned char *base, int off)
 {
-    return *(const Pair<R> *)(base + off);
+    Quad<R> q;
+    if constexpr (sizeof(R) == 8) {
+        const double2 v = *(const double2 *)(base + off);
+        q.a = v.x; q.b = v.y; q.th = -273.15; q.p = 0.0;
+    } else {
+        q = *(const Quad<R> *)(base + off);
+    }
+    return q;
 }
 
-// Register budget: four waves per SIMD for up to 4 nodes per lane (at most
-// 128 VGPRs; the few loop-invariant values that do not fit are re-read from
-// the L1-resident spill area each step, which costs far less than halving
-// the waves that hide the latency of the FP64 pipeline and of LDS), two
-// waves for 8 nodes per lane.
-template <int NPT> constexpr int res_waves_per_eu() { return NPT <= 4 ? 4 : 2; }
+// Register budget (waves per SIMD).  FP64 with up to 4 nodes per lane: four
+// waves (at most 128 VGPRs; the few loop-invariant values that do not fit
+// are re-read from the L1-resident spill area each step, which costs far
+// less than the waves that hide the latency of the FP64 pipeline and of
+// LDS).  FP32 issues at the VALU peak already and is sensitive to spill
+// traffic: three waves (168 VGPRs) where whole workgroups still fill them
+// (up to 256 lanes, one wave per SIMD each), four for 512 lanes (two waves
+// per SIMD each).  8 nodes per lane: two waves.  (Measured on the
+// 65,536 x 1001 batch: FP64 2 -> 4 waves +27 %; FP32 with four waves 6 %
+// slower than with three, with five 30 % slower.)
+template <typename R, int NPT, int NT> constexpr int res_waves_per_eu()
+{
+    return NPT > 4 ? 2 : (sizeof(R) == 8 || NT > 256 ? 4 : 3);
+}
 
 template <typename R, int NPT, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<NPT>())))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT>())))
 k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ block_walls,
               const int32_t *__restrict__ block_rooms, const WallDev *__restrict__ walls,
-              R *T0b, R *T1b, R *P0b, R *P1b, const uint8_t *__restrict__ lay,
-              const RoomDev *__restrict__ rooms, double *roomT, double *roomP,
-              const double *__restrict__ sched_go, const double *__restrict__ sched_qh,
-              double *__restrict__ flux, int *__restrict__ bad,
-              const int64_t *__restrict__ step_base, int ksteps, int mw, int mr, RunConst rc,
-              Shape sh)
+              const R *T0b, const R *T1b, const R *P0b, const R *P1b,
+              const uint8_t *__restrict__ lay, const RoomDev *__restrict__ rooms,
+              const double *roomT, const double *roomP, const double *__restrict__ sched_go,
+              const double *__restrict__ sched_qh, const double *flux,
+              const int64_t *__restrict__ step_base, const ResIO *__restrict__ io, int ksteps,
+              int mw, RunConst rc, Shape sh)
 {
     static_assert(NT >= 2 * kResMaxWalls, "one lane per wall side computes the ambient");
+    static_assert(sizeof(WallRec<R>) % 16 == 0, "records keep 16-byte alignment");
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int nthreads = NT;
-    const ResLds L = res_lds<R>(NT, mw, mr);
-    R *halo = (R *)(lds + L.halo);                      // [4][NT]
-    R *facb = (R *)(lds + L.face);                      // [2][NT]
-    double (*s_flux)[12] = (double (*)[12])(lds + L.flux);
-    double *s_surf = (double *)(lds + L.surf);          // [par][slot][side][T,P]
-    double *s_amb = (double *)(lds + L.amb);            // [par][slot][side][T,P]
-    double (*s_rot)[2][12] = (double (*)[2][12])(lds + L.rot);
-    double (*s_bc)[2][8] = (double (*)[2][8])(lds + L.bc);
-    double *s_room = (double *)(lds + L.room);          // [par][zone][T,P]
-    R *s_cc = (R *)(lds + L.cc);                        // [slot][layer][c0/r, cM0/r]
-    R *s_fk = (R *)(lds + L.fk);                        // [slot][entry][k0, kM0]
-    int32_t *s_wstart = (int32_t *)(lds + L.wstart);
-    int32_t *s_wid = (int32_t *)(lds + L.wid);
-    int32_t *s_wroom = (int32_t *)(lds + L.wroom);      // local zone or -1
-    int32_t *s_wside = (int32_t *)(lds + L.wside);      // side facing the zone
-    int32_t *s_rid = (int32_t *)(lds + L.rid);
-    auto SURF = [&](int par, int s, int side, int k) -> double & {
-        return s_surf[((par * mw + s) * 2 + side) * 2 + k];
-    };
-    auto AMB = [&](int par, int s, int side, int k) -> double & {
-        return s_amb[((par * mw + s) * 2 + side) * 2 + k];
-    };
-    auto ROOM = [&](int par, int z, int k) -> double & { return s_room[(par * mr + z) * 2 + k]; };
+    constexpr size_t kRc = res_off_rc<R>(NT), kWalls = res_off_walls<R>(NT);
+    R *halo = (R *)lds;                                  // [4][NT]
+    R *facb = halo + 4 * NT;                             // [2][NT]
+    double *s_rc = (double *)(lds + kRc);                // dt, Lv, rho_a, c_pa, c_pv, Pv_ref
+    WallRec<R> *wr = (WallRec<R> *)(lds + kWalls);
+    RoomRec *rr = (RoomRec *)(lds + kWalls + sizeof(WallRec<R>) * (size_t)mw);
 
     const int t = threadIdx.x;
     const ResBlock B = blocks[blockIdx.x];
@@ -156,38 +165,41 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     const int nrb = B.r_end - B.r_begin;
     const int64_t n0 = *step_base;
 
-    // ---- wall table, zone table
+    // ---- run constants, wall table, zone table
     if (t == 0) {
+        s_rc[0] = rc.dt; s_rc[1] = rc.Lv; s_rc[2] = rc.rho_a;
+        s_rc[3] = rc.c_pa; s_rc[4] = rc.c_pv; s_rc[5] = rc.Pv_ref;
         int acc = 0;
         for (int s = 0; s < nwb; ++s) {
             int w = block_walls[B.w_begin + s];
-            s_wid[s] = w;
-            s_wstart[s] = acc;
+            wr[s].wid = w;
+            wr[s].wstart = acc;
             acc += walls[w].nx;
+            wr[s].wend = acc;
         }
-        s_wstart[nwb] = acc;
     }
     if (t < nrb) {
         int r = block_rooms[B.r_begin + t];
-        s_rid[t] = r;
-        ROOM(n0 & 1, t, 0) = roomT[r];
-        ROOM(n0 & 1, t, 1) = roomP[r];
+        rr[t].rid = r;
+        rr[t].air[n0 & 1][0] = roomT[r];
+        rr[t].air[n0 & 1][1] = roomP[r];
     }
     __syncthreads();
     for (int q = t; q < nwb * 12; q += nthreads) {
         int s = q / 12, k = q % 12;
-        s_flux[s][k] = flux[(int64_t)s_wid[s] * 12 + k];
+        wr[s].flux[k] = flux[(int64_t)wr[s].wid * 12 + k];
     }
     // per-wall tables: zone link, surface constants, layer scales, face scales
     if (t < nwb) {
-        const WallDev &W = walls[s_wid[t]];
+        WallRec<R> &X = wr[t];
+        const WallDev &W = walls[X.wid];
         int lr = -1;
         for (int z = 0; z < nrb; ++z)
-            if (s_rid[z] == W.room) lr = z;
-        s_wroom[t] = lr;
-        s_wside[t] = W.room_side;
+            if (rr[z].rid == W.room) lr = z;
+        X.wroom = lr;
+        X.wside = W.room_side;
         for (int side = 0; side < 2; ++side) {
-            double *bc = s_bc[t][side];
+            double *bc = X.bc[side];
             bc[0] = W.dx;                       // s / r
             bc[1] = W.hT[side];
             bc[2] = W.hM[side];
@@ -198,26 +210,25 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             bc[7] = W.area;
         }
         const double rinv = 1.0 / W.r;
-        R *cc = s_cc + 6 * t;
-        R *fk = s_fk + 16 * t;
         for (int l = 0; l < 3; ++l) {
             const int la = l < W.n_layers ? l : 0;
-            cc[2 * l] = (R)(W.lay[la][L_C0] * rinv);
-            cc[2 * l + 1] = (R)(W.lay[la][L_CM0] * rinv);
-            fk[4 * l] = (R)W.lay[la][L_K0];
-            fk[4 * l + 1] = (R)W.lay[la][L_KM0];
+            X.cc[l][0] = (R)(W.lay[la][L_C0] * rinv);
+            X.cc[l][1] = (R)(W.lay[la][L_CM0] * rinv);
+            X.fk[2 * l][0] = (R)W.lay[la][L_K0];
+            X.fk[2 * l][1] = (R)W.lay[la][L_KM0];
             // interface with the next layer: harmonic mean, 0 when both are 0
             const int lb = l + 1 < W.n_layers ? l + 1 : la;
             double a = W.lay[la][L_K0], bb = W.lay[lb][L_K0];
             double am = W.lay[la][L_KM0], bm = W.lay[lb][L_KM0];
             double s1 = a + bb, s2 = am + bm;
-            fk[4 * l + 2] = (R)(s1 > 0.0 ? 2.0 * a * bb / s1 : 0.0);
-            fk[4 * l + 3] = (R)(s2 > 0.0 ? 2.0 * am * bm / s2 : 0.0);
+            X.fk[2 * l + 1][0] = (R)(s1 > 0.0 ? 2.0 * a * bb / s1 : 0.0);
+            X.fk[2 * l + 1][1] = (R)(s2 > 0.0 ? 2.0 * am * bm / s2 : 0.0);
         }
-        fk[2 * kFaceNone] = (R)0;
-        fk[2 * kFaceNone + 1] = (R)0;
-        fk[2 * kFaceNone + 2] = (R)0;
-        fk[2 * kFaceNone + 3] = (R)0;
+        X.cc[3][0] = X.cc[3][1] = (R)1;     // padding nodes: any finite capacity
+        for (int e = 0; e < 4; ++e) { X.cc[e][2] = Store<R>::thref(W); X.cc[e][3] = Store<R>::pref(W); }
+        for (int e = 0; e < 8; ++e) { X.fk[e][2] = Store<R>::thref(W); X.fk[e][3] = Store<R>::pref(W); }
+        X.fk[kFaceNone][0] = X.fk[kFaceNone][1] = (R)0;
+        X.fk[7][0] = X.fk[7][1] = (R)0;
     }
 
     // ---- ambient lanes: one per wall side; the outdoor sinusoids advance by
@@ -228,7 +239,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         const WallDev &W = walls[block_walls[B.w_begin + amb_slot]];
         const double *ST = W.Tamb[amb_side], *SR = W.RHamb[amb_side];
         const double t0 = (double)n0 * rc.dt;
-        double *st = s_rot[amb_slot][amb_side];
+        double *st = wr[amb_slot].rot[amb_side];
         st[0] = ST[0]; st[1] = ST[1]; st[2] = SR[0]; st[3] = SR[1];
         sincos(2.0 * dpi() * t0 / ST[2] + ST[3], &st[4], &st[5]);
         sincos(2.0 * dpi() * t0 / SR[2] + SR[3], &st[6], &st[7]);
@@ -245,7 +256,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
 
     R Ta_[NPT], Pa_[NPT], Tb_[NPT], Pb_[NPT];   // two level buffers (roles alternate)
     int info[NPT];
-    int coff[NPT], koff[NPT];                   // byte offsets into the scale tables
+    int coff[NPT], koff[NPT];                   // byte offsets of the scale pairs in LDS
     {
         int slot = 0;
 #pragma unroll
@@ -253,12 +264,12 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             const int b = t * NPT + q;
             Ta_[q] = Pa_[q] = Tb_[q] = Pb_[q] = 0;
             info[q] = kFaceNone << 13;
-            coff[q] = (int)L.cc;
-            koff[q] = (int)(L.fk + sizeof(R) * 2 * kFaceNone);
+            coff[q] = (int)(kWalls + offsetof(WallRec<R>, cc) + sizeof(R) * 4 * 3);
+            koff[q] = (int)(kWalls + offsetof(WallRec<R>, fk) + sizeof(R) * 4 * kFaceNone);
             if (b < B.n_nodes) {
-                while (b >= s_wstart[slot + 1]) ++slot;
-                const WallDev &W = walls[s_wid[slot]];
-                const int j = b - s_wstart[slot];
+                while (b >= wr[slot].wend) ++slot;
+                const WallDev &W = walls[wr[slot].wid];
+                const int j = b - wr[slot].wstart;
                 const int64_t g = (int64_t)W.off + j;
                 Ta_[q] = Tp[g]; Pa_[q] = Pp[g];
                 Tb_[q] = Tc[g]; Pb_[q] = Pc[g];
@@ -267,31 +278,18 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 if (j < W.nx - 1) fe = lay[g + 1] == la ? 2 * la : 2 * la + 1;
                 info[q] = slot | ((j == 0) << 8) | ((j == W.nx - 1) << 9) | (1 << 10) | (la << 11) |
                           (fe << 13);
-                coff[q] = (int)(L.cc + sizeof(R) * (6 * slot + 2 * la));
-                koff[q] = (int)(L.fk + sizeof(R) * (16 * slot + 2 * fe));
+                const int rb = (int)(kWalls + sizeof(WallRec<R>) * (size_t)slot);
+                coff[q] = rb + (int)(offsetof(WallRec<R>, cc) + sizeof(R) * 4 * la);
+                koff[q] = rb + (int)(offsetof(WallRec<R>, fk) + sizeof(R) * 4 * fe);
             }
         }
     }
     const R aT = (R)sh.aT, aM = (R)sh.aM, bTM = (R)sh.bTM, cT = (R)sh.cT, aC = (R)sh.aC,
             eTM = (R)sh.eTM, fTM = (R)sh.fTM;
-    // FP64 stores absolute values: references are constants; FP32 stores
-    // deviations from each wall's initial state
-    R thref[NPT], pref[NPT];
-#pragma unroll
-    for (int q = 0; q < NPT; ++q) {
-        if constexpr (sizeof(R) == 8) {
-            thref[q] = (R)-273.15;
-            pref[q] = (R)0;
-        } else {
-            const WallDev &W = walls[s_wid[info[q] & 0xff]];
-            thref[q] = Store<R>::thref(W);
-            pref[q] = Store<R>::pref(W);
-        }
-    }
     const R ps_inv = (R)(1.0 / 610.94);
     __syncthreads();
     int amb_zone = -1;
-    if (amb_lane && s_wroom[amb_slot] >= 0 && s_wside[amb_slot] == amb_side) amb_zone = s_wroom[amb_slot];
+    if (amb_lane && wr[amb_slot].wroom >= 0 && wr[amb_slot].wside == amb_side) amb_zone = wr[amb_slot].wroom;
 
     // One DF step from (Tm, Pm) = level n-1 and (Tn, Pn) = level n; leaves
     // level n+1 in (Tm, Pm).
@@ -299,11 +297,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                     const int64_t n) __attribute__((always_inline)) {
         const int par = (int)(n & 1);
         // ---- A: publish halos, surface values and the ambient at t^n
-        R *hp = halo;
-        hp[t] = Tn[0];
-        hp[nthreads + t] = Pn[0];
-        hp[2 * nthreads + t] = Tn[NPT - 1];
-        hp[3 * nthreads + t] = Pn[NPT - 1];
+        halo[t] = Tn[0];
+        halo[nthreads + t] = Pn[0];
+        halo[2 * nthreads + t] = Tn[NPT - 1];
+        halo[3 * nthreads + t] = Pn[NPT - 1];
         if (nrb > 0) {
 #pragma unroll
             for (int q = 0; q < NPT; ++q) {
@@ -311,23 +308,23 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 if (f & (3 << 8)) {
                     const int s = f & 0xff;
                     const int side = (f >> 8) & 1 ? 0 : 1;
-                    SURF(par, s, side, 0) = s_bc[s][side][6] + (double)Tn[q];
-                    SURF(par, s, side, 1) = (double)pref[q] + (double)Pn[q];
+                    wr[s].surf[par][side][0] = wr[s].bc[side][6] + (double)Tn[q];
+                    wr[s].surf[par][side][1] = (double)wr[s].cc[0][3] + (double)Pn[q];
                 }
             }
         }
         if (amb_lane) {
             double Ta, Pa;
-            double *st = s_rot[amb_slot][amb_side];
+            double *st = wr[amb_slot].rot[amb_side];
             if (amb_zone >= 0) {
-                Ta = ROOM(par, amb_zone, 0);
-                Pa = ROOM(par, amb_zone, 1);
+                Ta = rr[amb_zone].air[par][0];
+                Pa = rr[amb_zone].air[par][1];
             } else {
                 Ta = st[0] + st[1] * st[4];
                 Pa = (st[2] + st[3] * st[6]) * psat_th(Ta - 273.15);
             }
-            AMB(par, amb_slot, amb_side, 0) = Ta;
-            AMB(par, amb_slot, amb_side, 1) = Pa;
+            wr[amb_slot].amb[par][amb_side][0] = Ta;
+            wr[amb_slot].amb[par][amb_side][1] = Pa;
             const double sT = st[4], cTr = st[5], sR = st[6], cR = st[7];
             st[4] = fma(sT, st[9], cTr * st[8]);
             st[5] = fma(cTr, st[9], -sT * st[8]);
@@ -336,47 +333,50 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         }
         __syncthreads();
         // ---- B: faces and node humidity ratios, zones
-        const R Tr_nb = t + 1 < nthreads ? hp[t + 1] : (R)0;
-        const R Pr_nb = t + 1 < nthreads ? hp[nthreads + t + 1] : (R)0;
-        const R Tl_nb = t > 0 ? hp[2 * nthreads + t - 1] : (R)0;
-        const R Pl_nb = t > 0 ? hp[3 * nthreads + t - 1] : (R)0;
+        const R Tr_nb = t + 1 < nthreads ? halo[t + 1] : (R)0;
+        const R Pr_nb = t + 1 < nthreads ? halo[nthreads + t + 1] : (R)0;
+        const R Tl_nb = t > 0 ? halo[2 * nthreads + t - 1] : (R)0;
+        const R Pl_nb = t > 0 ? halo[3 * nthreads + t - 1] : (R)0;
         if (t < nrb) {
-            const RoomDev &Rm = rooms[s_rid[t]];
-            const double tt = (double)n * rc.dt;
-            const double Ta = ROOM(par, t, 0), Pa = ROOM(par, t, 1);
-            const double mass = rc.rho_a * Rm.volume;
+            const double dt = s_rc[0], Lv = s_rc[1], rho_a = s_rc[2], c_pa = s_rc[3];
+            const double c_pv = s_rc[4], Pv_ref = s_rc[5];
+            const RoomDev &Rm = rooms[rr[t].rid];
+            const double tt = (double)n * dt;
+            const double Ta = rr[t].air[par][0], Pa = rr[t].air[par][1];
+            const double mass = rho_a * Rm.volume;
             const double gv = Rm.ach * mass / 3600.0;
-            const double cma = rc.c_pa + rc.c_pv * Pa / rc.Pv_ref;
+            const double cma = c_pa + c_pv * Pa / Pv_ref;
             const int64_t slot = (int64_t)floor(tt / Rm.sched_dt) % Rm.n_sched;
             const double go = sched_go[Rm.sched_off + slot], Qh = sched_qh[Rm.sched_off + slot];
             const double Tout = sine_at(Rm.Tout, tt);
             const double Pout = sine_at(Rm.RHout, tt) * psat_th(Tout - 273.15);
-            double G = go + gv * (Pout - Pa) / rc.Pv_ref;
-            double Q = Qh + rc.Lv * go + gv * cma * (Tout - Ta) + rc.Lv * gv * (Pout - Pa) / rc.Pv_ref;
+            double G = go + gv * (Pout - Pa) / Pv_ref;
+            double Q = Qh + Lv * go + gv * cma * (Tout - Ta) + Lv * gv * (Pout - Pa) / Pv_ref;
             for (int s = 0; s < nwb; ++s) {
-                if (s_wroom[s] != t) continue;
-                const int side = s_wside[s];
-                const double *bc = s_bc[s][side];
-                const double Ts = SURF(par, s, side, 0), Ps = SURF(par, s, side, 1);
+                if (wr[s].wroom != t) continue;
+                const int side = wr[s].wside;
+                const double *bc = wr[s].bc[side];
+                const double Ts = wr[s].surf[par][side][0], Ps = wr[s].surf[par][side][1];
                 G += bc[7] * bc[2] * (Ps - Pa);
                 Q += bc[7] * (bc[1] * (Ts - Ta) + bc[3] * (Ps - Pa));
             }
-            ROOM(par ^ 1, t, 1) = Pa + rc.dt * G / (mass / rc.Pv_ref);
-            ROOM(par ^ 1, t, 0) = Ta + rc.dt * Q / (mass * cma);
+            rr[t].air[par ^ 1][1] = Pa + dt * G / (mass / Pv_ref);
+            rr[t].air[par ^ 1][0] = Ta + dt * Q / (mass * cma);
         }
         R kT[NPT], kM[NPT], phn[NPT];
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
-            const Pair<R> k0 = lds_pair<R>(lds, koff[q]);
+            const Quad<R> k0 = lds_scales<R>(lds, koff[q]);
+            const R thr = k0.th, pr = k0.p;
             // a node without a right face (wall end, padding) has zero scales;
             // its face state is its own, so that nothing from the next wall or
             // from padding enters its arithmetic (and no NaN can leak in)
             const bool live = (info[q] >> 13) != kFaceNone;
             const R Tr = live ? (q + 1 < NPT ? Tn[q + 1 < NPT ? q + 1 : q] : Tr_nb) : Tn[q];
             const R Pr = live ? (q + 1 < NPT ? Pn[q + 1 < NPT ? q + 1 : q] : Pr_nb) : Pn[q];
-            const R thn = thref[q] + Tn[q];
-            const R thf = fma((R)0.5, Tn[q] + Tr, thref[q]);
-            const R Pf = fma((R)0.5, Pn[q] + Pr, pref[q]);
+            const R thn = thr + Tn[q];
+            const R thf = fma((R)0.5, Tn[q] + Tr, thr);
+            const R Pf = fma((R)0.5, Pn[q] + Pr, pr);
             // Magnus exponents of face and node (FP64: one shared reciprocal)
             const R df = thf + (R)243.04, dn = thn + (R)243.04;
             R af, an;
@@ -391,23 +391,23 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             const R ef = exp_bounded(-(R)17.625 * af);
             const R en = exp_bounded(-(R)17.625 * an);
             const R phi = (Pf * ef) * ps_inv;               // phi = P / Ps
-            phn[q] = ((pref[q] + Pn[q]) * en) * ps_inv;
+            phn[q] = ((pr + Pn[q]) * en) * ps_inv;
             kT[q] = k0.a * fma(aT, phi, (R)1);
             kM[q] = k0.b * fma(aM * phi, phi, (R)1);
             SCHED_FENCE();
         }
-        R *fp = facb;
-        fp[t] = kT[NPT - 1];
-        fp[nthreads + t] = kM[NPT - 1];
+        facb[t] = kT[NPT - 1];
+        facb[nthreads + t] = kM[NPT - 1];
         __syncthreads();
         // ---- C: node updates (moisture, then heat with the new Pv)
-        const R klT = t > 0 ? fp[t - 1] : (R)0;
-        const R klM = t > 0 ? fp[nthreads + t - 1] : (R)0;
+        const R klT = t > 0 ? facb[t - 1] : (R)0;
+        const R klM = t > 0 ? facb[nthreads + t - 1] : (R)0;
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
             const int f = info[q];
-            const Pair<R> c0 = lds_pair<R>(lds, coff[q]);
-            const R th = thref[q] + Tn[q];
+            const Quad<R> c0 = lds_scales<R>(lds, coff[q]);
+            const R pr = c0.p;
+            const R th = c0.th + Tn[q];
             const R phi = phn[q];
             const R ccT = c0.a * fma(cT, phi, (R)1);
             const R ccM = c0.b * fma(aC, phi, (R)1);
@@ -444,17 +444,18 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             } else {
                 const int s = f & 0xff;
                 const int side = (f >> 8) & 1 ? 0 : 1;
-                const double *bc = s_bc[s][side];
+                WallRec<R> &X = wr[s];
+                const double *bc = X.bc[side];
                 const R k_T = side == 0 ? kT[q] : lT;
                 const R k_M = side == 0 ? kM[q] : lM;
                 const R k_X = side == 0 ? kXq : lX;
                 const R Tnb = side == 0 ? Tr : Tl;
                 const R Pnb = side == 0 ? Pr : Pl;
-                const double Tinf = AMB(par, s, side, 0);
-                const double Pinf = AMB(par, s, side, 1);
+                const double Tinf = X.amb[par][side][0];
+                const double Pinf = X.amb[par][side][1];
                 const double tref = bc[6];
                 const R Tid = (R)(Tinf - tref);
-                const R Pid = (R)(Pinf - (double)pref[q]);
+                const R Pid = (R)(Pinf - (double)pr);
                 const R d = (R)bc[0];                      // s / r
                 const R hT = (R)bc[1], hM = (R)bc[2];
                 const R hL = (R)bc[3];
@@ -482,16 +483,17 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 if constexpr (sizeof(R) == 8) Tnew = rhs * (dM * inv);
                 else Tnew = div_nr(rhs, dT);
                 // applied flux (FP64) and its compensated integral
+                const double dt = s_rc[0];
                 const double Ts = 0.5 * ((double)Tnew + (double)Tm[q]);
                 const double Ps = 0.5 * ((double)Pnew + (double)Pm[q]);
-                const double g = bc[2] * ((Pinf - (double)pref[q]) - Ps) + bc[4];
+                const double g = bc[2] * ((Pinf - (double)pr) - Ps) + bc[4];
                 const double qh = bc[1] * ((Tinf - tref) - Ts)
-                                + bc[3] * ((Pinf - (double)pref[q]) - Ps) + bc[5];
-                double *fw = s_flux[s];
+                                + bc[3] * ((Pinf - (double)pr) - Ps) + bc[5];
+                double *fw = X.flux;
                 fw[side * 2] = qh;
                 fw[side * 2 + 1] = g;
-                neumaier_add(fw[4 + side * 2], fw[8 + side * 2], rc.dt * qh);
-                neumaier_add(fw[5 + side * 2], fw[9 + side * 2], rc.dt * g);
+                neumaier_add(fw[4 + side * 2], fw[8 + side * 2], dt * qh);
+                neumaier_add(fw[5 + side * 2], fw[9 + side * 2], dt * g);
             }
             if (!(f & (1 << 10))) { Tnew = 0; Pnew = 0; }
             Tm[q] = Tnew;   // level n-1 is no longer needed by node q
@@ -518,11 +520,12 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     // now (Ta_, Pa_) = level n0+k-1 and (Tb_, Pb_) = level n0+k
 
     // ---- write back: level n0+k and n0+k-1, fluxes, zone air
+    const ResIO O = *io;
     const int64_t nend = n0 + ksteps;
-    R *Tw_cur = (nend & 1) ? T1b : T0b;
-    R *Pw_cur = (nend & 1) ? P1b : P0b;
-    R *Tw_prv = (nend & 1) ? T0b : T1b;
-    R *Pw_prv = (nend & 1) ? P0b : P1b;
+    R *Tw_cur = (R *)O.T[nend & 1];
+    R *Pw_cur = (R *)O.P[nend & 1];
+    R *Tw_prv = (R *)O.T[(nend & 1) ^ 1];
+    R *Pw_prv = (R *)O.P[(nend & 1) ^ 1];
     int nonfinite = 0;
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
@@ -530,8 +533,8 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         if (f & (1 << 10)) {
             const int b = t * NPT + q;
             const int s = f & 0xff;
-            const WallDev &W = walls[s_wid[s]];
-            const int64_t g = (int64_t)W.off + (b - s_wstart[s]);
+            const WallDev &W = O.walls[wr[s].wid];
+            const int64_t g = (int64_t)W.off + (b - wr[s].wstart);
             if (!(isfinite(Tb_[q]) && isfinite(Pb_[q]))) nonfinite = 1;
             Tw_cur[g] = Tb_[q];
             Pw_cur[g] = Pb_[q];
@@ -539,15 +542,15 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             Pw_prv[g] = Pa_[q];
         }
     }
-    if (nonfinite) atomicOr(bad, 1);
+    if (nonfinite) atomicOr(O.bad, 1);
     __syncthreads();
     for (int q = t; q < nwb * 12; q += nthreads) {
         int s = q / 12, k = q % 12;
-        flux[(int64_t)s_wid[s] * 12 + k] = s_flux[s][k];
+        O.flux[(int64_t)wr[s].wid * 12 + k] = wr[s].flux[k];
     }
     if (t < nrb) {
-        roomT[s_rid[t]] = ROOM(nend & 1, t, 0);
-        roomP[s_rid[t]] = ROOM(nend & 1, t, 1);
+        O.roomT[rr[t].rid] = rr[t].air[nend & 1][0];
+        O.roomP[rr[t].rid] = rr[t].air[nend & 1][1];
     }
 }
 

@@ -43,6 +43,9 @@ struct dfhm_ctx {
     double *d_flux = nullptr;
     int *d_bad = nullptr;
     int64_t *d_step = nullptr;
+    ResIO *d_io = nullptr;         // write-back pointers of the resident kernel
+    ResIO io_host{};               // what d_io holds
+    bool io_valid = false;
     // zones
     void *room_mem = nullptr;
     RoomDev *d_rooms = nullptr;
@@ -426,6 +429,7 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
     size_t ob = take(sizeof(ResBlock) * blocks.size());
     size_t ow = take(sizeof(int32_t) * bw.size());
     size_t orr = take(sizeof(int32_t) * br.size());
+    size_t oio = take(sizeof(ResIO));
     if (c->pack_mem) { (void)hipStreamSynchronize(c->stream); (void)hipFree(c->pack_mem); c->pack_mem = nullptr; }
     void *mem = nullptr;
     if (hipMalloc(&mem, o) != hipSuccess) return fail(c, DFHM_E_NOMEM, "packing tables");
@@ -433,6 +437,8 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
     c->d_blocks = (ResBlock *)((char *)mem + ob);
     c->d_block_walls = (int32_t *)((char *)mem + ow);
     c->d_block_rooms = (int32_t *)((char *)mem + orr);
+    c->d_io = (ResIO *)((char *)mem + oio);
+    c->io_valid = false;
     HIP_TRY(c, hipMemcpyAsync(c->d_blocks, blocks.data(), sizeof(ResBlock) * blocks.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_block_walls, bw.data(), sizeof(int32_t) * bw.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_block_rooms, br.data(), sizeof(int32_t) * br.size(), hipMemcpyHostToDevice, c->stream));
@@ -490,25 +496,44 @@ dfhm_status ensure_packing(dfhm_ctx *c)
     return pack(c, nt, npt);
 }
 
+// The resident kernel reads its write-back pointers from device memory;
+// refresh them when the level buffers or the zone arrays have moved.
+void refresh_io(dfhm_ctx *c)
+{
+    ResIO io{};
+    io.T[0] = c->d_T[0]; io.T[1] = c->d_T[1];
+    io.P[0] = c->d_P[0]; io.P[1] = c->d_P[1];
+    io.walls = c->d_walls;
+    io.flux = c->d_flux;
+    io.roomT = c->d_roomT;
+    io.roomP = c->d_roomP;
+    io.bad = c->d_bad;
+    if (c->io_valid && std::memcmp(&io, &c->io_host, sizeof io) == 0) return;
+    c->io_host = io;
+    (void)hipMemcpyAsync(c->d_io, &c->io_host, sizeof io, hipMemcpyHostToDevice, c->stream);
+    c->io_valid = true;
+}
+
 template <typename R, int NPT, int NT>
 void launch_res(dfhm_ctx *c, int k)
 {
+    refresh_io(c);
     static bool attr_set = false;   // the largest tables need more than 64 KB of LDS
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)res_lds<R>(NT, kResMaxWalls, kResMaxRooms).total);
+                                  (int)res_lds_bytes<R>(NT, kResMaxWalls, kResMaxRooms));
         attr_set = true;
     }
-    // LDS tables sized by the largest wall / zone count of a workgroup of
+    // LDS records sized by the largest wall / zone count of a workgroup of
     // this packing (at least one of each)
     const int mw = std::max(1, c->max_wpb), mr = std::max(1, c->max_rpb);
     hipLaunchKernelGGL((k_df_resident<R, NPT, NT>), dim3(c->n_blocks), dim3(NT),
-                       res_lds<R>(NT, mw, mr).total, c->stream, c->d_blocks, c->d_block_walls,
-                       c->d_block_rooms, c->d_walls, (R *)c->d_T[0], (R *)c->d_T[1],
-                       (R *)c->d_P[0], (R *)c->d_P[1], c->d_lay, c->d_rooms, c->d_roomT,
-                       c->d_roomP, c->d_go, c->d_qh, c->d_flux, c->d_bad, c->d_step, k, mw, mr,
-                       c->rc, c->shape);
+                       res_lds_bytes<R>(NT, mw, mr), c->stream, c->d_blocks, c->d_block_walls,
+                       c->d_block_rooms, c->d_walls, (const R *)c->d_T[0], (const R *)c->d_T[1],
+                       (const R *)c->d_P[0], (const R *)c->d_P[1], c->d_lay, c->d_rooms,
+                       c->d_roomT, c->d_roomP, c->d_go, c->d_qh, c->d_flux, c->d_step, c->d_io, k,
+                       mw, c->rc, c->shape);
 }
 
 template <typename R>
