@@ -51,42 +51,66 @@ enum {
 
 constexpr int GB_M = 128, GB_N = 128, GB_K = 32, G_PAD = 8;
 
-// Load a 128 x 32 tile of an operand into LDS as [row][k] (k contiguous).
-// rows = M or N index, K multiple of 8, rows multiple of 8 (zero outside).
+// A 128 x 32 operand tile moves global -> registers (fetch) -> LDS (put),
+// stored in LDS as [row][k] (k contiguous).  rows = M or N index, K multiple
+// of 8, rows multiple of 8 (zero outside).  Each of the 256 lanes holds 32 B.
+struct TileRegs { uint4 v[2]; };
+
 template <int LAYOUT>
-__device__ __forceinline__ void load_tile(uint16_t (*s)[GB_K + G_PAD], const uint16_t *__restrict__ g,
-                                          int ld, int row0, int nrows, int k0, int kend, int tid)
+__device__ __forceinline__ TileRegs fetch_tile(const uint16_t *__restrict__ g, int ld, int row0,
+                                               int nrows, int k0, int kend, int tid)
 {
+    TileRegs r;
     if (LAYOUT == OP_K) {
-        const int r = tid >> 1;                 // 128 rows, 2 threads per row
+        const int rr = tid >> 1;                 // 128 rows, 2 lanes per row
         const int kk = (tid & 1) * 16;
-        const int gr = row0 + r;
+        const int gr = row0 + rr;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int gk = k0 + kk + 8 * h;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (gr < nrows && gk < kend) v = *(const uint4 *)(g + (int64_t)gr * ld + gk);
-            *(uint4 *)&s[r][kk + 8 * h] = v;
+            r.v[h] = make_uint4(0, 0, 0, 0);
+            if (gr < nrows && gk < kend) r.v[h] = *(const uint4 *)(g + (int64_t)gr * ld + gk);
         }
     } else {
-        const int kk = tid >> 3;                // 32 k, 8 threads per k
-        const int rr = (tid & 7) * 16;
+        const int kk = tid >> 3;                 // 32 k, 8 lanes per k
+        const int rb = (tid & 7) * 16;
         const int gk = k0 + kk;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int gr = row0 + rr + 8 * h;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (gr < nrows && gk < kend) v = *(const uint4 *)(g + (int64_t)gk * ld + gr);
-            const uint16_t *e = (const uint16_t *)&v;
+            const int gr = row0 + rb + 8 * h;
+            r.v[h] = make_uint4(0, 0, 0, 0);
+            if (gr < nrows && gk < kend) r.v[h] = *(const uint4 *)(g + (int64_t)gk * ld + gr);
+        }
+    }
+    return r;
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void put_tile(uint16_t (*s)[GB_K + G_PAD], const TileRegs &r, int tid)
+{
+    if (LAYOUT == OP_K) {
+        const int rr = tid >> 1;
+        const int kk = (tid & 1) * 16;
+        *(uint4 *)&s[rr][kk] = r.v[0];
+        *(uint4 *)&s[rr][kk + 8] = r.v[1];
+    } else {
+        const int kk = tid >> 3;
+        const int rb = (tid & 7) * 16;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) s[rr + 8 * h + q][kk] = e[q];
+        for (int h = 0; h < 2; ++h) {
+            const uint16_t *e = (const uint16_t *)&r.v[h];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s[rb + 8 * h + q][kk] = e[q];
         }
     }
 }
 
 // One 128 x 128 output tile per workgroup of 256 lanes (2 x 2 waves of
-// 64 x 64, each a 4 x 4 grid of 16 x 16 MFMA tiles, K step 32).  Split-K:
-// blockIdx.z covers K range [z * kchunk, (z+1) * kchunk).
+// 64 x 64, each a 4 x 4 grid of 16 x 16 MFMA tiles, K step 32).  The K loop
+// is software-pipelined: the next K tile is fetched into registers while the
+// MFMAs consume the current one from LDS, and LDS is double-buffered, so a
+// K step needs one barrier.  Split-K: blockIdx.z covers K range
+// [z * kchunk, (z+1) * kchunk).
 template <int LA, int LB, int EPI>
 __global__ void __launch_bounds__(256)
 k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
@@ -94,8 +118,8 @@ k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
             uint16_t *__restrict__ Cb, int ldc, const float *__restrict__ bias,
             const uint16_t *__restrict__ aux, uint16_t *__restrict__ pre, int kchunk)
 {
-    __shared__ __align__(16) uint16_t sA[GB_M][GB_K + G_PAD];
-    __shared__ __align__(16) uint16_t sB[GB_N][GB_K + G_PAD];
+    __shared__ __align__(16) uint16_t sA[2][GB_M][GB_K + G_PAD];
+    __shared__ __align__(16) uint16_t sB[2][GB_N][GB_K + G_PAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -111,21 +135,37 @@ k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
 
     const int fr = lane & 15;          // row (A) / column (B) inside a 16 x 16 tile
     const int fk = (lane >> 4) * 8;    // this lane's 8 reduction indices
-    for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
-        load_tile<LA>(sA, A, lda, m0, M, k0, kend, tid);
-        load_tile<LB>(sB, B, ldb, n0, N, k0, kend, tid);
+    if (kbeg < kend) {
+        TileRegs ra = fetch_tile<LA>(A, lda, m0, M, kbeg, kend, tid);
+        TileRegs rb = fetch_tile<LB>(B, ldb, n0, N, kbeg, kend, tid);
+        put_tile<LA>(sA[0], ra, tid);
+        put_tile<LB>(sB[0], rb, tid);
         __syncthreads();
-        bf16x8 af[4], bfr[4];
+        int buf = 0;
+        for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
+            const bool more = k0 + GB_K < kend;
+            if (more) {
+                ra = fetch_tile<LA>(A, lda, m0, M, k0 + GB_K, kend, tid);
+                rb = fetch_tile<LB>(B, ldb, n0, N, k0 + GB_K, kend, tid);
+            }
+            bf16x8 af[4], bfr[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8 *)&sA[wm * 64 + i * 16 + fr][fk];
+            for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8 *)&sA[buf][wm * 64 + i * 16 + fr][fk];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bfr[j] = *(const bf16x8 *)&sB[wn * 64 + j * 16 + fr][fk];
+            for (int j = 0; j < 4; ++j) bfr[j] = *(const bf16x8 *)&sB[buf][wn * 64 + j * 16 + fr][fk];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            if (more) {
+                // the other buffer was last read before the previous barrier
+                put_tile<LA>(sA[buf ^ 1], ra, tid);
+                put_tile<LB>(sB[buf ^ 1], rb, tid);
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
     }
     // accumulator layout: lane holds rows 4*(lane/16)+r, column lane%16
     const int rbase = (lane >> 4) * 4;

@@ -161,6 +161,25 @@ def test_edge_sizes(sname, sched):
     compare(s, ref, dfhm.FP64, f"edges {sname}")
 
 
+@pytest.mark.parametrize("pname,prec", PRECS)
+def test_full_workgroup_of_small_walls(pname, prec):
+    """66 walls of at most 16 nodes (26 layered, Nx capped by the stability
+    rule): the resident packing fills one workgroup with its maximum of 64
+    walls and puts the rest into another, so every per-wall LDS record slot
+    is used."""
+    walls = wl.concat(wl.uniform_batch(40, seed=60, nx=16, L=0.3),
+                      wl.layered_batch(26, seed=61, nx_lo=16, nx_hi=16, dt=10.0))
+    cfg = wl.default_config(dt=10.0)
+    say(f"64-wall workgroup {pname}")
+    ref = oracle_run(walls, cfg, 500)
+    s = dfhm.Solver(walls, cfg, precision=prec, schedule=dfhm.SCHED_RESIDENT, chunk=128,
+                    threads=256, npt=4)
+    s.step(500)
+    s.sync()
+    assert s.info()["max_walls_per_block"] == 64
+    compare(s, ref, prec, f"64 walls {pname}")
+
+
 @pytest.mark.parametrize("sname,sched", SCHEDS)
 def test_restart_from_given_levels(sname, sched):
     """dfhm_set_fields + dfhm_set_step_index: continue from two given levels."""
