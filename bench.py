@@ -146,20 +146,42 @@ def roofline(dtype, cells, steps, ms, info):
             "launch_ms": round(per_launch_s * 1e3, 4)}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(walls_fn, cfg, n_walls, steps):
+    """The FP64 oracle on the host threads (at most 16, the machine's CPU share)
+    over a bounded sample of the batch, plus a single-thread figure."""
     import oracle
     oracle.build()
     walls = walls_fn(n_walls)
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else (os.cpu_count() or 1)))
     sim = oracle.RefSim(walls, cfg)
     sim.step(1, threads=threads)          # start-up step outside the timing
     t = time.perf_counter()
     sim.step(steps, threads=threads)
     dt = time.perf_counter() - t
     cells = int(np.sum(walls["nx"])) * steps
+    one = oracle.RefSim(walls_fn(16), cfg)
+    one.step(1, threads=1)
+    t1 = time.perf_counter()
+    one.step(steps // 5, threads=1)
+    dt1 = time.perf_counter() - t1
+    cells1 = 16 * NX * (steps // 5)
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": cells1 / dt1, "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
             "sample": f"{n_walls} walls x {NX} nodes x {steps} steps of the same batch "
-                      f"(FP64 C oracle, OpenMP over walls), {dt:.1f} s"}
+                      f"(FP64 C oracle, OpenMP over walls), {dt:.1f} s; single thread: 16 walls x "
+                      f"{steps // 5} steps, {dt1:.1f} s"}
 
 
 def other_workload(a, torch, dfhm, wl):
