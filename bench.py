@@ -53,10 +53,13 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--walls", type=int, default=N_WALLS)
-    ap.add_argument("--workload", default="identical", choices=["identical", "layered", "building"],
+    ap.add_argument("--workload", default="identical",
+                    choices=["identical", "layered", "building", "implicit"],
                     help="identical: the 65,536 x 1001 batch (the default and the headline); "
                          "layered: 100,000 uneven 1-3 layer walls (FP32, dt = 1 s); "
-                         "building: 4,096 rooms x 6 walls coupled to the room-air balance")
+                         "building: 4,096 rooms x 6 walls coupled to the room-air balance; "
+                         "implicit: the identical batch through the Euler-implicit and "
+                         "Crank-Nicolson comparators against DF")
     ap.add_argument("--rooms", type=int, default=4096)
     ap.add_argument("--shape", default=None,
                     help="resident launch shape THREADSxNODES (e.g. 256x4); default: the library's")
@@ -216,6 +219,40 @@ def other_workload(a, torch, dfhm, wl):
     print(json.dumps(out), flush=True)
 
 
+def implicit_workload(a, torch, dfhm, wl):
+    """DF against the implicit comparators (fixed-point sub-iterations,
+    eta = 1e-10) on the identical-grid batch at the same dt: cost per step."""
+    walls = wl.uniform_batch(a.walls, seed=202, nx=NX)
+    cfg = wl.default_config(dt=DT)
+    cells = a.walls * NX
+    out = {"metric": "DF vs implicit comparator, cell-updates/s at equal dt", "unit": "cell-updates/s",
+           "n_gpus": 1, "data": "synthetic", "higher_is_better": True,
+           "config": {"workload": "identical-grid batch: 65,536 walls x 1001 nodes (30 cm), dt = 1 s",
+                      "walls": a.walls, "nx": NX, "dt_s": DT}}
+    ms, info, fin = run_gpu(dfhm, walls, cfg, dfhm.FP64, a.schedule, a.steps, a.warmup)
+    out["df_fp64"] = {"value": cells * a.steps / (ms / 1e3), "ms_per_step": ms / a.steps,
+                      "steps": a.steps}
+    steps = max(1, min(a.steps, 50))
+    stream = torch.cuda.current_stream()
+    for name, theta in (("euler_implicit", 1.0), ("crank_nicolson", 0.5)):
+        ic = dfhm.Implicit(walls, dt=DT, theta=theta, eta=1e-10, max_iters=200)
+        ic.step(2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ic.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ims = e0.elapsed_time(e1)
+        it = ic.iterations()
+        out[name] = {"value": cells * steps / (ims / 1e3), "ms_per_step": ims / steps, "steps": steps,
+                     "mean_sub_iterations": it,
+                     "df_cost_fraction": (ms / a.steps) / (ims / steps)}
+        ic.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     global SHAPE
@@ -236,6 +273,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.workload == "implicit":
+        implicit_workload(a, torch, dfhm, wl)
+        return
     if a.workload != "identical":
         other_workload(a, torch, dfhm, wl)
         return

@@ -199,6 +199,43 @@ dfhm_status dfhm_get_info(const dfhm_ctx *ctx, dfhm_info *info);
 dfhm_status dfhm_autotune(dfhm_ctx *ctx, int32_t probe_steps);
 
 /* ---------------------------------------------------------------------
+ * Implicit comparator (Sec. 5.2 and Algorithm 1): the theta-scheme in time
+ * (theta = 1 Euler implicit, 1/2 Crank-Nicolson) on the same grid and law as
+ * the DF scheme, with fixed-point sub-iterations on the coefficients
+ * (evaluated at the theta-weighted state between level n and the current
+ * iterate, faces at the face-averaged state) and one tridiagonal solve per
+ * field and sub-iteration, moisture first, heat with the new vapour
+ * pressure.  A sub-iteration loop stops when the largest change of T and of
+ * Pv is at most eta times the largest |T| and |Pv|, or after max_iters.  FP64,
+ * walls with the outdoor air on both sides (zones are not coupled), from the
+ * walls' uniform initial state; no start-up step (two-level scheme).  For
+ * measuring what the explicit DF scheme saves against it.
+ * ------------------------------------------------------------------- */
+typedef struct dfhm_implicit dfhm_implicit;
+typedef struct {
+    double dt_s;           /* > 0 */
+    double theta;          /* in [0.5, 1] */
+    double eta;            /* > 0, relative fixed-point tolerance */
+    int32_t max_iters;     /* >= 1 sub-iterations per step */
+    int32_t reserved;
+    double Lv;             /* 0 -> 2.5e6 J/kg */
+    void *stream;          /* hipStream_t or NULL */
+} dfhm_implicit_config;
+/* Walls as for dfhm_create (side 1 uses T_amb[1] / RH_amb[1]).  Allocates
+ * 7 doubles per node (walls grouped by 64, each group padded to its longest
+ * wall).  DFHM_E_INVAL on a bad descriptor or configuration. */
+dfhm_status dfhm_implicit_create(const dfhm_implicit_config *cfg, const dfhm_wall *walls,
+                                 int64_t n_walls, dfhm_implicit **out);
+/* Queue n_steps steps on the stream (asynchronous). */
+dfhm_status dfhm_implicit_step_n(dfhm_implicit *ic, int64_t n_steps);
+/* T and Pv (host, nx values each) of one wall at the current step; synchronises. */
+dfhm_status dfhm_implicit_get_fields(dfhm_implicit *ic, int64_t wall, double *T, double *Pv);
+/* Mean sub-iterations per wall and step so far; synchronises. */
+dfhm_status dfhm_implicit_iterations(dfhm_implicit *ic, double *mean_per_step);
+int64_t dfhm_implicit_step_index(const dfhm_implicit *ic);
+void dfhm_implicit_destroy(dfhm_implicit *ic);
+
+/* ---------------------------------------------------------------------
  * Surface-flux surrogate (not part of the paper): an MLP mapping a wall's
  * recent outdoor history and parameters to the next interval's mean interior
  * surface fluxes, with BF16 weights / activations and FP32 accumulation on

@@ -18,6 +18,7 @@
 #include "../../include/dfhm.h"
 #include "df_kernels.hpp"
 #include "df_resident.hpp"
+#include "df_implicit.hpp"
 
 using namespace dfhm;
 
@@ -1004,6 +1005,139 @@ dfhm_status dfhm_get_info(const dfhm_ctx *c, dfhm_info *info)
     info->step_index = c->n;
     info->pack_efficiency = c->pack_eff;
     return DFHM_OK;
+}
+
+// ------------------------------------------------------ implicit comparator
+
+struct dfhm_implicit {
+    dfhm_implicit_config cfg{};
+    hipStream_t stream = nullptr;
+    int64_t nw = 0, n = 0, slots = 0;
+    int ngroups = 0;
+    std::vector<WallDev> walls;
+    std::vector<ImpGroup> groups;
+    void *mem = nullptr;
+    WallDev *d_walls = nullptr;
+    ImpGroup *d_groups = nullptr;
+    ImpArrays A{};
+    int64_t *d_iters = nullptr;
+    std::string err;
+};
+
+dfhm_status dfhm_implicit_create(const dfhm_implicit_config *cfg, const dfhm_wall *walls,
+                                 int64_t n_walls, dfhm_implicit **out)
+{
+    if (!out) return DFHM_E_INVAL;
+    *out = nullptr;
+    if (!cfg || !walls || n_walls < 1) return DFHM_E_INVAL;
+    if (!(std::isfinite(cfg->dt_s) && cfg->dt_s > 0.0) || !(cfg->theta >= 0.5 && cfg->theta <= 1.0) ||
+        !(cfg->eta > 0.0) || cfg->max_iters < 1)
+        return DFHM_E_INVAL;
+    for (int64_t i = 0; i < n_walls; ++i)
+        if (!check_wall(walls[i], i).empty()) return DFHM_E_INVAL;
+    dfhm_implicit *ic = new (std::nothrow) dfhm_implicit();
+    if (!ic) return DFHM_E_NOMEM;
+    ic->cfg = *cfg;
+    ic->cfg.Lv = orz(cfg->Lv, 2.5e6);
+    ic->stream = (hipStream_t)cfg->stream;
+    ic->nw = n_walls;
+    ic->walls.resize(n_walls);
+    for (int64_t i = 0; i < n_walls; ++i) fill_wall(ic->walls[i], walls[i], 0);
+    // groups of 64 consecutive walls, each a node-major block padded to its longest wall
+    int64_t base = 0;
+    for (int64_t w0 = 0; w0 < n_walls; w0 += kImpLanes) {
+        ImpGroup g;
+        g.base = base;
+        g.w0 = (int32_t)w0;
+        g.nw = (int32_t)std::min<int64_t>(kImpLanes, n_walls - w0);
+        int maxnx = 0;
+        for (int k = 0; k < g.nw; ++k) maxnx = std::max(maxnx, (int)walls[w0 + k].nx);
+        base += (int64_t)maxnx * kImpLanes;
+        ic->groups.push_back(g);
+    }
+    ic->slots = base;
+    ic->ngroups = (int)ic->groups.size();
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    const size_t ow = take(sizeof(WallDev) * n_walls), og = take(sizeof(ImpGroup) * ic->ngroups);
+    size_t oa[7];
+    for (int k = 0; k < 7; ++k) oa[k] = take(sizeof(double) * (size_t)base);
+    const size_t oi = take(sizeof(int64_t) * n_walls);
+    if (hipMalloc(&ic->mem, o) != hipSuccess) { delete ic; return DFHM_E_NOMEM; }
+    char *m = (char *)ic->mem;
+    ic->d_walls = (WallDev *)(m + ow);
+    ic->d_groups = (ImpGroup *)(m + og);
+    ic->A.T[0] = (double *)(m + oa[0]); ic->A.T[1] = (double *)(m + oa[1]);
+    ic->A.P[0] = (double *)(m + oa[2]); ic->A.P[1] = (double *)(m + oa[3]);
+    ic->A.Pn = (double *)(m + oa[4]); ic->A.cp = (double *)(m + oa[5]); ic->A.dp = (double *)(m + oa[6]);
+    ic->d_iters = (int64_t *)(m + oi);
+    auto bail = [&]() { dfhm_implicit_destroy(ic); return DFHM_E_DEVICE; };
+    if (hipMemcpyAsync(ic->d_walls, ic->walls.data(), sizeof(WallDev) * n_walls, hipMemcpyHostToDevice, ic->stream) != hipSuccess ||
+        hipMemcpyAsync(ic->d_groups, ic->groups.data(), sizeof(ImpGroup) * ic->ngroups, hipMemcpyHostToDevice, ic->stream) != hipSuccess ||
+        hipMemsetAsync(ic->d_iters, 0, sizeof(int64_t) * n_walls, ic->stream) != hipSuccess)
+        return bail();
+    hipLaunchKernelGGL(k_init_walls, dim3((unsigned)((n_walls + 63) / 64)), dim3(64), 0, ic->stream,
+                       ic->d_walls, (int)n_walls, cfg->dt_s);
+    hipLaunchKernelGGL(k_imp_init, dim3(ic->ngroups), dim3(kImpLanes), 0, ic->stream, ic->d_walls,
+                       ic->d_groups, ic->A);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ic->stream) != hipSuccess) return bail();
+    *out = ic;
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_implicit_step_n(dfhm_implicit *ic, int64_t n_steps)
+{
+    if (!ic || n_steps < 0) return DFHM_E_INVAL;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        hipLaunchKernelGGL(k_imp_step, dim3(ic->ngroups), dim3(kImpLanes), 0, ic->stream, ic->d_walls,
+                           ic->d_groups, ic->A, ic->n, ic->cfg.dt_s, ic->cfg.theta, ic->cfg.eta,
+                           (int)ic->cfg.max_iters, ic->cfg.Lv, ic->d_iters);
+        ic->n += 1;
+    }
+    if (hipGetLastError() != hipSuccess) { ic->err = "kernel launch failed"; return DFHM_E_DEVICE; }
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_implicit_get_fields(dfhm_implicit *ic, int64_t wall, double *T, double *Pv)
+{
+    if (!ic || !T || !Pv || wall < 0 || wall >= ic->nw) return DFHM_E_INVAL;
+    const ImpGroup &g = ic->groups[wall / kImpLanes];
+    const int lane = (int)(wall % kImpLanes), nx = ic->walls[wall].nx;
+    const int p = (int)(ic->n & 1);
+    // one strided copy per field: element j of the wall is at base + 64 j + lane
+    if (hipMemcpy2DAsync(T, sizeof(double), ic->A.T[p] + g.base + lane, sizeof(double) * kImpLanes,
+                         sizeof(double), nx, hipMemcpyDeviceToHost, ic->stream) != hipSuccess ||
+        hipMemcpy2DAsync(Pv, sizeof(double), ic->A.P[p] + g.base + lane, sizeof(double) * kImpLanes,
+                         sizeof(double), nx, hipMemcpyDeviceToHost, ic->stream) != hipSuccess ||
+        hipStreamSynchronize(ic->stream) != hipSuccess) {
+        ic->err = "copy failed";
+        return DFHM_E_DEVICE;
+    }
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_implicit_iterations(dfhm_implicit *ic, double *mean_per_step)
+{
+    if (!ic || !mean_per_step) return DFHM_E_INVAL;
+    std::vector<int64_t> it(ic->nw);
+    if (hipMemcpyAsync(it.data(), ic->d_iters, sizeof(int64_t) * ic->nw, hipMemcpyDeviceToHost, ic->stream) != hipSuccess ||
+        hipStreamSynchronize(ic->stream) != hipSuccess)
+        return DFHM_E_DEVICE;
+    double s = 0.0;
+    for (int64_t v : it) s += (double)v;
+    *mean_per_step = ic->n > 0 ? s / ((double)ic->nw * (double)ic->n) : 0.0;
+    return DFHM_OK;
+}
+
+int64_t dfhm_implicit_step_index(const dfhm_implicit *ic) { return ic ? ic->n : -1; }
+
+void dfhm_implicit_destroy(dfhm_implicit *ic)
+{
+    if (!ic) return;
+    if (ic->stream) (void)hipStreamSynchronize(ic->stream);
+    else (void)hipDeviceSynchronize();
+    if (ic->mem) (void)hipFree(ic->mem);
+    delete ic;
 }
 
 // ------------------------------------------------------------ checkpoints

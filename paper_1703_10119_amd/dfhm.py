@@ -74,6 +74,13 @@ class Info(C.Structure):
                 ("step_index", C.c_int64), ("pack_efficiency", C.c_double)]
 
 
+class ImplicitConfig(C.Structure):
+    """dfhm_implicit_config"""
+    _fields_ = [("dt_s", C.c_double), ("theta", C.c_double), ("eta", C.c_double),
+                ("max_iters", C.c_int32), ("reserved", C.c_int32), ("Lv", C.c_double),
+                ("stream", C.c_void_p)]
+
+
 class MlpConfig(C.Structure):
     """dfhm_mlp_config"""
     _fields_ = [("n_in", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
@@ -94,6 +101,8 @@ EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_step_n",
            "dfhm_set_step_index", "dfhm_get_rooms", "dfhm_get_info", "dfhm_autotune",
            "dfhm_step_index", "dfhm_last_error", "dfhm_status_string", "dfhm_destroy",
            "dfhm_save", "dfhm_load",
+           "dfhm_implicit_create", "dfhm_implicit_step_n", "dfhm_implicit_get_fields",
+           "dfhm_implicit_iterations", "dfhm_implicit_step_index", "dfhm_implicit_destroy",
            "dfhm_mlp_create", "dfhm_mlp_param_count", "dfhm_mlp_get_params",
            "dfhm_mlp_set_params", "dfhm_mlp_forward", "dfhm_mlp_gradients",
            "dfhm_mlp_train_step", "dfhm_mlp_last_error", "dfhm_mlp_destroy",
@@ -142,6 +151,17 @@ def load(path: str = LIB_PATH):
     L.dfhm_load.argtypes = [P, P, C.c_size_t]
     L.dfhm_save.restype = C.c_int
     L.dfhm_load.restype = C.c_int
+    L.dfhm_implicit_create.argtypes = [C.POINTER(ImplicitConfig), C.POINTER(Wall), I64, C.POINTER(P)]
+    L.dfhm_implicit_step_n.argtypes = [P, I64]
+    L.dfhm_implicit_get_fields.argtypes = [P, I64, P, P]
+    L.dfhm_implicit_iterations.argtypes = [P, C.POINTER(C.c_double)]
+    L.dfhm_implicit_step_index.restype = I64
+    L.dfhm_implicit_step_index.argtypes = [P]
+    L.dfhm_implicit_destroy.restype = None
+    L.dfhm_implicit_destroy.argtypes = [P]
+    for f in (L.dfhm_implicit_create, L.dfhm_implicit_step_n, L.dfhm_implicit_get_fields,
+              L.dfhm_implicit_iterations):
+        f.restype = C.c_int
     # surface-flux surrogate
     L.dfhm_mlp_create.argtypes = [C.POINTER(MlpConfig), C.POINTER(P)]
     L.dfhm_mlp_param_count.restype = I64
@@ -390,3 +410,61 @@ class Solver:
 
     def autotune(self, probe_steps: int = 50):
         self._check(load().dfhm_autotune(self._h, int(probe_steps)), "dfhm_autotune")
+
+
+class Implicit:
+    """Batched implicit comparator (theta-scheme with fixed-point
+    sub-iterations) on the current HIP device: dfhm_implicit_*."""
+
+    def __init__(self, walls: dict, dt: float, theta: float = 1.0, eta: float = 1e-10,
+                 max_iters: int = 200, Lv: float = 0.0, stream=None):
+        import torch
+        L = load()
+        c = ImplicitConfig()
+        c.dt_s, c.theta, c.eta, c.max_iters, c.Lv = float(dt), float(theta), float(eta), int(max_iters), float(Lv)
+        c.stream = torch.cuda.current_stream().cuda_stream if stream is None else stream
+        self.W = len(walls["nx"])
+        self.nx = np.asarray(walls["nx"], np.int64)
+        arr = walls_struct_fast(walls) if self.W > 256 else walls_struct(walls)
+        h = C.c_void_p()
+        st = L.dfhm_implicit_create(C.byref(c), arr, self.W, C.byref(h))
+        if st != 0:
+            raise DfhmError(st, "dfhm_implicit_create")
+        self._h = h
+
+    def step(self, nsteps: int):
+        st = load().dfhm_implicit_step_n(self._h, int(nsteps))
+        if st != 0:
+            raise DfhmError(st, "dfhm_implicit_step_n")
+
+    def fields(self, w: int):
+        nx = int(self.nx[w])
+        T = np.empty(nx)
+        P = np.empty(nx)
+        st = load().dfhm_implicit_get_fields(self._h, int(w), T.ctypes.data_as(C.c_void_p),
+                                             P.ctypes.data_as(C.c_void_p))
+        if st != 0:
+            raise DfhmError(st, "dfhm_implicit_get_fields")
+        return T, P
+
+    def iterations(self) -> float:
+        m = C.c_double(0.0)
+        st = load().dfhm_implicit_iterations(self._h, C.byref(m))
+        if st != 0:
+            raise DfhmError(st, "dfhm_implicit_iterations")
+        return m.value
+
+    @property
+    def n(self) -> int:
+        return int(load().dfhm_implicit_step_index(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dfhm_implicit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""GPU parity of the batched implicit comparator (dfhm_implicit_*) against
+the oracle's theta-scheme with fixed-point sub-iterations (Sec. 5.2,
+Algorithm 1), FP64.
+
+Tolerance: both sides stop their fixed point when the largest change is at
+most eta = 1e-12 of the field scale; what is left is that stopping error and
+the rounding of two tridiagonal solves per sub-iteration, so 1e-10 relative
+(max-norm per field) bounds the difference.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1703_10119_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1703_10119_amd import dfhm  # noqa: E402
+
+TOL = 1e-10
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_uniform_walls_match_oracle(theta):
+    """70 walls (two groups of lanes), 101 nodes, dt = 60 s, 40 steps."""
+    walls = wl.uniform_batch(70, seed=21, nx=101, L=0.1)
+    ic = dfhm.Implicit(walls, dt=60.0, theta=theta, eta=1e-12, max_iters=200)
+    ic.step(40)
+    for w in (0, 31, 63, 64, 69):
+        T, P = ic.fields(w)
+        Tr, Pr, it = oracle.implicit_run(walls, w, 60.0, wl.LV, 40, theta=theta, eta=1e-12)
+        eT, eP = rel(T, Tr), rel(P, Pr)
+        print(f"theta={theta} wall {w}: T {eT:.2e} P {eP:.2e} (oracle {it:.2f} sub-iterations)")
+        assert eT <= TOL and eP <= TOL, (w, eT, eP)
+    m = ic.iterations()
+    print("mean sub-iterations per step", m)
+    assert 2.0 <= m < 200.0
+    ic.close()
+
+
+def test_layered_walls_match_oracle():
+    """Uneven walls with 1-3 layers (harmonic interfaces), Crank-Nicolson."""
+    walls = wl.layered_batch(12, seed=23, nx_lo=20, nx_hi=300, dt=30.0)
+    ic = dfhm.Implicit(walls, dt=30.0, theta=0.5, eta=1e-12)
+    ic.step(30)
+    worst = 0.0
+    for w in range(12):
+        T, P = ic.fields(w)
+        Tr, Pr, _ = oracle.implicit_run(walls, w, 30.0, wl.LV, 30, theta=0.5, eta=1e-12)
+        worst = max(worst, rel(T, Tr), rel(P, Pr))
+    print("layered worst", worst)
+    assert worst <= TOL
+    ic.close()
+
+
+def test_implicit_and_df_agree_at_small_dt():
+    """Two schemes of the same problem: Crank-Nicolson and DF at dt = 1 s over
+    one hour differ only by their O(dt^2) truncation (and DF's
+    (dt/dx)^2 term), far below the field variation."""
+    walls = wl.uniform_batch(4, seed=25, nx=101, L=0.1)
+    cfg = wl.default_config(dt=1.0)
+    ic = dfhm.Implicit(walls, dt=1.0, theta=0.5, eta=1e-12)
+    ic.step(3600)
+    s = dfhm.Solver(walls, cfg, precision=dfhm.FP64, schedule=dfhm.SCHED_RESIDENT)
+    s.step(3600)
+    for w in range(4):
+        T, P = ic.fields(w)
+        Td, Pd = s.fields(w)
+        dT = np.max(np.abs(T - Td)) / np.ptp(Td)
+        dP = np.max(np.abs(P - Pd)) / np.ptp(Pd)
+        print(f"wall {w}: |CN - DF| / range: T {dT:.2e} P {dP:.2e}")
+        assert dT < 1e-2 and dP < 1e-2
+    ic.close()
+    s.close()
+
+
+def test_bad_configuration_is_refused():
+    walls = wl.uniform_batch(2, seed=1, nx=11, L=0.1)
+    for kw in (dict(theta=0.3), dict(theta=1.1), dict(eta=0.0), dict(max_iters=0), dict(dt=0.0)):
+        args = dict(dt=1.0, theta=1.0, eta=1e-10, max_iters=10)
+        args.update(kw)
+        with pytest.raises(dfhm.DfhmError):
+            dfhm.Implicit(walls, **args)
