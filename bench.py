@@ -246,9 +246,16 @@ def implicit_workload(a, torch, dfhm, wl):
         torch.cuda.synchronize()
         ims = e0.elapsed_time(e1)
         it = ic.iterations()
+        # algorithmic HBM bytes per node and sub-iteration: the two forward
+        # sweeps read 4 + 5 values and write 2 + 2, the two back
+        # substitutions read 3 + 4 and write 1 + 2 (8 B each): 200 B
+        gbs = 200.0 * cells * it / (ims / 1e3 / steps) / 1e9
         out[name] = {"value": cells * steps / (ims / 1e3), "ms_per_step": ims / steps, "steps": steps,
                      "mean_sub_iterations": it,
-                     "df_cost_fraction": (ms / a.steps) / (ims / steps)}
+                     "df_cost_fraction": (ms / a.steps) / (ims / steps),
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK,
+                                  "unit": "GB/s", "frac": round(gbs / HBM_PEAK, 4), "traffic": None,
+                                  "kernel": "k_imp_step"}}
         ic.close()
     print(json.dumps(out), flush=True)
 
