@@ -50,14 +50,16 @@ class _Wall(C.Structure):
                 ("hT", C.c_double * 2), ("hM", C.c_double * 2),
                 ("qinf", C.c_double * 2), ("ginf", C.c_double * 2),
                 ("Tamb", _Sine * 2), ("RHamb", _Sine * 2),
-                ("T0", C.c_double), ("RH0", C.c_double), ("area", C.c_double)]
+                ("T0", C.c_double), ("RH0", C.c_double), ("area", C.c_double),
+                ("emis", C.c_double * 2), ("qsun", _Sine * 2)]
 
 
 class _Room(C.Structure):
     _fields_ = [("volume", C.c_double), ("ach", C.c_double), ("T0", C.c_double),
                 ("RH0", C.c_double), ("Tout", _Sine), ("RHout", _Sine),
                 ("n_sched", C.c_int32), ("sched_dt", C.c_double),
-                ("g_o", C.POINTER(C.c_double)), ("Q_h", C.POINTER(C.c_double))]
+                ("g_o", C.POINTER(C.c_double)), ("Q_h", C.POINTER(C.c_double)),
+                ("view", C.c_double)]
 
 
 class _Cfg(C.Structure):
@@ -115,6 +117,12 @@ def _walls_struct(walls: dict):
     W = len(walls["nx"])
     arr = (_Wall * max(W, 1))()
     lay = np.asarray(walls["layer"], np.float64)
+    # radiation inputs are optional in a wall set (absent = none)
+    emis = walls.get("emis", np.zeros((W, 2)))
+    qsun = walls.get("qsun")
+    if qsun is None:
+        qsun = np.zeros((W, 2, 4))
+        qsun[..., 2] = 86400.0
     for w in range(W):
         x = arr[w]
         x.nx = int(walls["nx"][w])
@@ -129,6 +137,8 @@ def _walls_struct(walls: dict):
             x.ginf[s] = float(walls["ginf"][w, s])
             _fill_sine(x.Tamb[s], walls["Tamb"][w, s])
             _fill_sine(x.RHamb[s], walls["RHamb"][w, s])
+            x.emis[s] = float(emis[w, s])
+            _fill_sine(x.qsun[s], qsun[w, s])
         x.T0 = float(walls["T0"][w])
         x.RH0 = float(walls["RH0"][w])
         x.area = float(walls["area"][w])
@@ -178,6 +188,7 @@ class RefSim:
                 x.sched_dt = float(rooms["sched_dt"][r])
                 x.g_o = go.ctypes.data_as(C.POINTER(C.c_double))
                 x.Q_h = qh.ctypes.data_as(C.POINTER(C.c_double))
+                x.view = float(rooms["view"][r]) if "view" in rooms else 0.0
         self._wr = np.ascontiguousarray(walls.get("wall_room", np.full(self.W, -1)), np.int64)
         self._rs = np.ascontiguousarray(walls.get("room_side", np.ones(self.W)), np.int8)
         if rooms is None:

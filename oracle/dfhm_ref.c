@@ -45,7 +45,17 @@
  *     outward normal, so fluxes are positive into the wall on both sides;
  *   - start of the three-level scheme: either m forward-Euler sub-steps of
  *     dt/m for the first step (m from the explicit stability bound at the
- *     initial state, with a safety factor 2), or u^{-1} := u^0.
+ *     initial state, with a safety factor 2), or u^{-1} := u^0;
+ *   - radiation in the surface heat source q_inf of eq. (2.3) (Sec. 2): on
+ *     every side, a constant part plus an incident flux max(0, sinusoid of
+ *     t) (the paper's outside radiation is only shown in a figure); on a
+ *     zone side, in addition, the long-wave exchange with the other surfaces
+ *     of the zone, s eps sigma sum_w (T_w^4 - T^4), with s the zone's view
+ *     factor, eps the emissivity of the receiving surface and T_w the
+ *     zone-side surface temperatures of all walls of the zone.  Both are
+ *     taken at t^n and level n, explicitly like the zone air; the start-up
+ *     step holds the long-wave part at level 0 and re-evaluates the
+ *     incident flux at every sub-step like the outdoor air.
  */
 #include <math.h>
 #include <stdint.h>
@@ -71,6 +81,8 @@ typedef struct {
     double hT[2], hM[2], qinf[2], ginf[2];
     ref_sine Tamb[2], RHamb[2];
     double T0, RH0, area;
+    double emis[2];       /* emissivity of each surface (zone side only) */
+    ref_sine qsun[2];     /* incident radiation, clipped at zero */
 } ref_wall;
 
 typedef struct {
@@ -80,6 +92,7 @@ typedef struct {
     double sched_dt;
     const double *g_o;  /* kg/s, piecewise constant, periodic */
     const double *Q_h;  /* W */
+    double view;        /* view factor s between two surfaces of the zone */
 } ref_room;
 
 typedef struct {
@@ -149,6 +162,16 @@ static double sine_at(const ref_sine *s, double t)
 {
     return s->mean + s->amp * sin(2.0 * REF_PI * t / s->period + s->phase);
 }
+
+/* Incident radiation (W/m2) on one side at time t: the sinusoid clipped at
+ * zero (no negative absorbed flux). */
+static double incident(const ref_wall *w, int side, double t)
+{
+    double q = sine_at(&w->qsun[side], t);
+    return q > 0.0 ? q : 0.0;
+}
+
+#define REF_SIGMA 5.670374419e-8   /* Stefan-Boltzmann constant, W/(m2 K4) */
 
 /* -------------------------------------------------------------- geometry */
 
@@ -312,11 +335,12 @@ static void ambient(const ref_sim *s, int64_t w, int side, double t,
  *    (c_TT + 2rk_TT + 2s h_T) T+ = (c_TT - 2rk_TT - 2s h_T) T- + 4rk_TT T_nb + 4s h_T T_inf
  *        + (c_TM - 2rk_TM - 2s Lv h_M) P- - (c_TM + 2rk_TM + 2s Lv h_M) P+
  *        + 4rk_TM P_nb + 4s Lv h_M P_inf + 4s q_inf
+ *  where q_inf = the wall's constant source + qx (radiation at t^n, level n).
  */
 static void df_wall_step(const ref_wall *w, const int *lay, double dt, double Lv,
                          const double *Tp, const double *Tc, const double *Pp,
                          const double *Pc, double *Tn, double *Pn,
-                         const double Tinf[2], const double Pinf[2],
+                         const double Tinf[2], const double Pinf[2], const double qx[2],
                          double flux[2][2], ref_kcoef *kf /* scratch nx-1 */)
 {
     int nx = w->nx;
@@ -367,7 +391,7 @@ static void df_wall_step(const ref_wall *w, const int *lay, double dt, double Lv
                        + (c.cTM - 2.0 * r * kX - 2.0 * sd * hL) * Pp[j]
                        - (c.cTM + 2.0 * r * kX + 2.0 * sd * hL) * Pn[j]
                        + 4.0 * r * kX * Pc[jn] + 4.0 * sd * hL * Pinf[side]
-                       + 4.0 * sd * w->qinf[side];
+                       + 4.0 * sd * (w->qinf[side] + qx[side]);
             Tn[j] = rhs / (c.cTT + 2.0 * r * kT + 2.0 * sd * hT);
         }
     }
@@ -379,7 +403,7 @@ static void df_wall_step(const ref_wall *w, const int *lay, double dt, double Lv
         double Ps = 0.5 * (Pn[j] + Pp[j]);
         double g = w->hM[side] * (Pinf[side] - Ps) + w->ginf[side];
         double q = w->hT[side] * (Tinf[side] - Ts)
-                 + Lv * w->hM[side] * (Pinf[side] - Ps) + w->qinf[side];
+                 + Lv * w->hM[side] * (Pinf[side] - Ps) + (w->qinf[side] + qx[side]);
         flux[side][0] = q;
         flux[side][1] = g;
     }
@@ -431,7 +455,8 @@ static int64_t ftcs_substeps(double dt, double bound)
  */
 static void ftcs_startup(const ref_sim *s, int64_t w, const int *lay, double *T,
                          double *P, double *Tw, double *Pw, ref_kcoef *kf,
-                         double flux_now[2][2], double *fsum, double *fcmp)
+                         const double qlw[2], double flux_now[2][2], double *fsum,
+                         double *fcmp)
 {
     const ref_wall *wl = &s->walls[w];
     int nx = wl->nx;
@@ -442,16 +467,18 @@ static void ftcs_startup(const ref_sim *s, int64_t w, const int *lay, double *T,
     double acc[2][2] = {{0, 0}, {0, 0}};
     for (int64_t k = 0; k < m; ++k) {
         double t = (double)k * dt / (double)m;
-        double Tinf[2], Pinf[2];
-        for (int side = 0; side < 2; ++side)
+        double Tinf[2], Pinf[2], qs[2];
+        for (int side = 0; side < 2; ++side) {
             ambient(s, w, side, t, s->Ta, s->Pa, &Tinf[side], &Pinf[side]);
+            qs[side] = wl->qinf[side] + (incident(wl, side, t) + qlw[side]);
+        }
         for (int j = 0; j < nx - 1; ++j) kf[j] = face_k(wl, lay, T, P, j);
         /* fluxes applied during this sub-step (surface value at its start) */
         for (int side = 0; side < 2; ++side) {
             int j = side == 0 ? 0 : nx - 1;
             double g = wl->hM[side] * (Pinf[side] - P[j]) + wl->ginf[side];
             double q = wl->hT[side] * (Tinf[side] - T[j])
-                     + Lv * wl->hM[side] * (Pinf[side] - P[j]) + wl->qinf[side];
+                     + Lv * wl->hM[side] * (Pinf[side] - P[j]) + qs[side];
             neumaier_add(&fsum[side * 2 + 0], &fcmp[side * 2 + 0], dts * q);
             neumaier_add(&fsum[side * 2 + 1], &fcmp[side * 2 + 1], dts * g);
             acc[side][0] += q;
@@ -475,7 +502,7 @@ static void ftcs_startup(const ref_sim *s, int64_t w, const int *lay, double *T,
                 int side = j == 0 ? 0 : 1;
                 dM += wl->hM[side] * (Pinf[side] - P[j]) + wl->ginf[side];
                 dT += wl->hT[side] * (Tinf[side] - T[j])
-                    + Lv * wl->hM[side] * (Pinf[side] - P[j]) + wl->qinf[side];
+                    + Lv * wl->hM[side] * (Pinf[side] - P[j]) + qs[side];
             }
             double Pnew = P[j] + dts * dM / (c.cM * width);
             /* c_TT dT/dt + c_TM dP/dt = (heat flux divergence) */
@@ -488,6 +515,27 @@ static void ftcs_startup(const ref_sim *s, int64_t w, const int *lay, double *T,
     }
     for (int side = 0; side < 2; ++side)
         for (int f = 0; f < 2; ++f) flux_now[side][f] = acc[side][f] / (double)m;
+}
+
+/* Long-wave exchange (W/m2, into the wall) received by the zone-side surface
+ * of wall w from the zone-side surfaces of all walls of its zone (Sec. 2,
+ * boundary conditions), at the level-n surface temperatures; 0 on a wall
+ * without a zone. */
+static double longwave(const ref_sim *s, int64_t w)
+{
+    int64_t r = s->wall_room[w];
+    if (r < 0) return 0.0;
+    const ref_wall *wl = &s->walls[w];
+    int side = s->room_side[w];
+    double T = s->Tc[s->off[w] + (side == 0 ? 0 : wl->nx - 1)];
+    double sum = 0.0;
+    for (int64_t v = 0; v < s->nw; ++v) {
+        if (s->wall_room[v] != r) continue;
+        const ref_wall *vl = &s->walls[v];
+        double Tv = s->Tc[s->off[v] + (s->room_side[v] == 0 ? 0 : vl->nx - 1)];
+        sum += Tv * Tv * Tv * Tv - T * T * T * T;
+    }
+    return s->rooms[r].view * wl->emis[side] * REF_SIGMA * sum;
 }
 
 /* Room air at step n -> n+1 by forward Euler (eq. LAV_equation with
@@ -535,9 +583,11 @@ int ref_step(ref_sim *s, int64_t nsteps, int nthreads)
 #endif
     double *Ta_new = (double *)malloc(sizeof(double) * (size_t)(s->nr > 0 ? s->nr : 1));
     double *Pa_new = (double *)malloc(sizeof(double) * (size_t)(s->nr > 0 ? s->nr : 1));
+    double *qlw = (double *)malloc(sizeof(double) * (size_t)(s->nw > 0 ? s->nw : 1));
     for (int64_t it = 0; it < nsteps; ++it) {
         double t = (double)s->n * s->cfg.dt;
         for (int64_t r = 0; r < s->nr; ++r) room_step(s, r, t, &Ta_new[r], &Pa_new[r]);
+        for (int64_t w = 0; w < s->nw; ++w) qlw[w] = longwave(s, w);
 #pragma omp parallel
         {
             ref_kcoef *kf = (ref_kcoef *)malloc(sizeof(ref_kcoef) * (size_t)maxnx);
@@ -552,10 +602,13 @@ int ref_step(ref_sim *s, int64_t nsteps, int nthreads)
                 int nx = wl->nx;
                 double *fs = s->fsum + 4 * w, *fc = s->fcmp + 4 * w;
                 double fl[2][2];
+                /* long-wave part on the zone side only (level n) */
+                double ql[2] = {0.0, 0.0};
+                if (s->wall_room[w] >= 0) ql[s->room_side[w]] = qlw[w];
                 if (s->n == 0 && s->cfg.startup == 0) {
                     memcpy(Tx, s->Tc + o, sizeof(double) * (size_t)nx);
                     memcpy(Px, s->Pc + o, sizeof(double) * (size_t)nx);
-                    ftcs_startup(s, w, s->lay + o, Tx, Px, Tw, Pw, kf, fl, fs, fc);
+                    ftcs_startup(s, w, s->lay + o, Tx, Px, Tw, Pw, kf, ql, fl, fs, fc);
                     memcpy(s->Tp + o, s->Tc + o, sizeof(double) * (size_t)nx);
                     memcpy(s->Pp + o, s->Pc + o, sizeof(double) * (size_t)nx);
                     memcpy(s->Tc + o, Tx, sizeof(double) * (size_t)nx);
@@ -565,12 +618,14 @@ int ref_step(ref_sim *s, int64_t nsteps, int nthreads)
                         memcpy(s->Tp + o, s->Tc + o, sizeof(double) * (size_t)nx);
                         memcpy(s->Pp + o, s->Pc + o, sizeof(double) * (size_t)nx);
                     }
-                    double Tinf[2], Pinf[2];
-                    for (int side = 0; side < 2; ++side)
+                    double Tinf[2], Pinf[2], qx[2];
+                    for (int side = 0; side < 2; ++side) {
                         ambient(s, w, side, t, s->Ta, s->Pa, &Tinf[side], &Pinf[side]);
+                        qx[side] = incident(wl, side, t) + ql[side];
+                    }
                     df_wall_step(wl, s->lay + o, s->cfg.dt, s->cfg.Lv,
                                  s->Tp + o, s->Tc + o, s->Pp + o, s->Pc + o,
-                                 Tw, Pw, Tinf, Pinf, fl, kf);
+                                 Tw, Pw, Tinf, Pinf, qx, fl, kf);
                     /* rotate: n -> n-1, n+1 -> n */
                     memcpy(s->Tp + o, s->Tc + o, sizeof(double) * (size_t)nx);
                     memcpy(s->Pp + o, s->Pc + o, sizeof(double) * (size_t)nx);
@@ -591,6 +646,7 @@ int ref_step(ref_sim *s, int64_t nsteps, int nthreads)
     }
     free(Ta_new);
     free(Pa_new);
+    free(qlw);
     return 0;
 }
 
@@ -792,9 +848,11 @@ double ref_implicit_run(const ref_wall *w, double dt, double Lv, int64_t nsteps,
                     int side = j == 0 ? 0 : 1;
                     double hT = w->hT[side], hL = Lv * w->hM[side];
                     diag += theta * hT;
-                    rhs += theta * (hT * Ti1[side] + hL * (Pi1[side] - Pn[j]) + w->qinf[side])
+                    double q1 = w->qinf[side] + incident(w, side, t1);
+                    double q0 = w->qinf[side] + incident(w, side, t0);
+                    rhs += theta * (hT * Ti1[side] + hL * (Pi1[side] - Pn[j]) + q1)
                          + (1.0 - theta) * (hT * (Ti0[side] - To[j])
-                                            + hL * (Pi0[side] - Po[j]) + w->qinf[side]);
+                                            + hL * (Pi0[side] - Po[j]) + q0);
                 }
                 b[j] = diag; d[j] = rhs;
             }

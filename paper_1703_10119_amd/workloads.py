@@ -17,10 +17,14 @@ A wall set is a dict of arrays (W walls, 3 layer slots):
     hT, hM, qinf, ginf [W, 2] f64  (side 0 = x = 0, side 1 = x = L),
     Tamb, RHamb [W, 2, 4] f64      (mean, amplitude, period s, phase rad),
     T0, RH0, area [W] f64,
+    emis [W, 2] f64                (surface emissivity, used on a room side),
+    qsun [W, 2, 4] f64             (incident radiation sinusoid, clipped at 0),
     wall_room [W] int64 (-1 = no room), room_side [W] int8.
 
 A room set is a dict:  volume, ach, T0, RH0 [R]; Tout, RHout [R, 4];
-sched_dt [R]; g_o, Q_h [R, S] (kg/s and W, periodic piecewise constant).
+sched_dt [R]; g_o, Q_h [R, S] (kg/s and W, periodic piecewise constant);
+view [R] (view factor between two surfaces of the room; 0 = no long-wave
+exchange).
 """
 from __future__ import annotations
 
@@ -59,6 +63,12 @@ def default_config(dt: float = 1.0, startup: int = 0) -> dict:
                 Pv_ref=1.61e5, startup=int(startup))
 
 
+def _zero_sine(shape) -> np.ndarray:
+    s = np.zeros(tuple(shape) + (4,))
+    s[..., 2] = DAY
+    return s
+
+
 def _empty_walls(W: int) -> dict:
     return dict(
         nx=np.zeros(W, np.int32),
@@ -68,6 +78,7 @@ def _empty_walls(W: int) -> dict:
         qinf=np.zeros((W, 2)), ginf=np.zeros((W, 2)),
         Tamb=np.zeros((W, 2, 4)), RHamb=np.zeros((W, 2, 4)),
         T0=np.zeros(W), RH0=np.zeros(W), area=np.ones(W),
+        emis=np.zeros((W, 2)), qsun=_zero_sine((W, 2)),
         wall_room=np.full(W, -1, np.int64), room_side=np.ones(W, np.int8),
     )
 
@@ -243,6 +254,7 @@ def building_batch(n_rooms: int, seed: int = 404, nx_lo: int = 101,
         sched_dt=np.full(R, 3600.0),
         g_o=rng.uniform(0.0, 0.5, (R, n_sched)) / 3600.0,   # kg/s
         Q_h=rng.uniform(0.0, 1000.0, (R, n_sched)),
+        view=np.zeros(R),
     )
     _sine(rooms["Tout"], 293.0, AT, DAY, pT)
     _sine(rooms["RHout"], 0.6, AR, DAY / 2, pR)
