@@ -87,7 +87,18 @@ typedef struct {
  * the harmonic mean of the two layers' conductivities at the face state
  * (zero when both are zero).  T_amb / RH_amb give the outdoor air of each
  * side (ignored on a side coupled to a room).  T0 / RH0 give the uniform
- * initial state (Pv0 = RH0 Ps(T0)).  area_m2 is used by the room balance. */
+ * initial state (Pv0 = RH0 Ps(T0)).  area_m2 is used by the room balance.
+ *
+ * Radiation (Sec. 2, the heat source q_inf of the boundary condition eq.
+ * (2.3)): the heat source of side s at t^n is
+ *     q_inf[s] + max(0, q_sun[s](t^n))
+ *       + (side coupled to a zone)  s_z eps[s] sigma sum_w (T_w^4 - T^4),
+ * the last term being the long-wave exchange with the zone-side surfaces of
+ * all walls of the zone (T_w, T: level-n zone-side surface temperatures in K,
+ * sigma = 5.670374419e-8 W/(m2 K4), s_z the zone's view_factor, eps the
+ * emissivity of the receiving surface).  All three enter the surface node
+ * explicitly and are part of the reported heat flux.  The start-up step
+ * holds the long-wave term at level 0 and evaluates q_sun at each sub-step. */
 typedef struct {
     int32_t nx, n_layers;           /* 3 <= nx <= 2048, 1 <= n_layers <= 3 */
     dfhm_layer layer[3];
@@ -95,6 +106,9 @@ typedef struct {
     double q_inf[2], g_inf[2];      /* extra heat / liquid flux into the wall */
     dfhm_sine T_amb[2], RH_amb[2];
     double T0, RH0, area_m2;
+    double emissivity[2];           /* in [0, 1]; used on a zone side only */
+    dfhm_sine q_sun[2];             /* incident radiation, W/m2, clipped at 0
+                                       (period_s > 0 even when unused) */
 } dfhm_wall;
 
 /* One perfectly mixed zone (Sec. 5.1): w ~ Pv / Pv_ref, ventilation flow
@@ -109,6 +123,8 @@ typedef struct {
     double sched_dt_s;              /* > 0 */
     const double *g_o_kg_s;         /* [n_sched] host */
     const double *Q_h_W;            /* [n_sched] host */
+    double view_factor;             /* s between two surfaces of the zone, in
+                                       [0, 1]; 0 = no long-wave exchange */
 } dfhm_room;
 
 typedef struct {

@@ -133,14 +133,17 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
     const int64_t b0 = G.base + lane;
     auto at = [&](int j) { return b0 + (int64_t)j * kImpLanes; };
 
-    // outdoor air at t^n and t^{n+1} on both sides
-    double Ti0[2], Pi0[2], Ti1[2], Pi1[2];
+    // outdoor air and surface heat sources (constant + incident radiation)
+    // at t^n and t^{n+1} on both sides
+    double Ti0[2], Pi0[2], Ti1[2], Pi1[2], Q0[2], Q1[2];
     for (int side = 0; side < 2; ++side) {
         const double t0 = (double)n * dt, t1 = (double)(n + 1) * dt;
         Ti0[side] = sine_at(W.Tamb[side], t0);
         Pi0[side] = sine_at(W.RHamb[side], t0) * psat_th(Ti0[side] - 273.15);
         Ti1[side] = sine_at(W.Tamb[side], t1);
         Pi1[side] = sine_at(W.RHamb[side], t1) * psat_th(Ti1[side] - 273.15);
+        Q0[side] = W.qinf[side] + incident(W, side, t0);
+        Q1[side] = W.qinf[side] + incident(W, side, t1);
     }
 
     // Each sweep keeps the data of the next kPf nodes in a register ring:
@@ -289,8 +292,8 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
                             const int side = j == 0 ? 0 : 1;
                             const double hT = W.hT[side], hL = Lv * W.hM[side];
                             diag += theta * hT;
-                            rhs += theta * (hT * Ti1[side] + hL * (Pi1[side] - Pnj) + W.qinf[side])
-                                 + th1 * (hT * (Ti0[side] - Toj) + hL * (Pi0[side] - Poj) + W.qinf[side]);
+                            rhs += theta * (hT * Ti1[side] + hL * (Pi1[side] - Pnj) + Q1[side])
+                                 + th1 * (hT * (Ti0[side] - Toj) + hL * (Pi0[side] - Poj) + Q0[side]);
                         }
                         const double den = diag - a * cpl;
                         cpl = c / den;

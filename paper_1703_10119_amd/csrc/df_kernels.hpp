@@ -89,6 +89,26 @@ __device__ __forceinline__ void ambient(const WallDev &W, int side, double t,
     }
 }
 
+// Long-wave exchange received by the zone-side surface of W (Sec. 2,
+// boundary conditions): s eps sigma (S4 - m T^4) with S4 the sum of T_w^4 over
+// the zone-side surfaces of the m walls of the zone, all read from the level
+// buffer Tg (whole batch) and Ts the surface temperature of W itself (K).
+template <typename R>
+__device__ __forceinline__ double longwave(const WallDev &W, const WallDev *__restrict__ walls,
+                                           const RoomDev *__restrict__ rooms,
+                                           const int32_t *__restrict__ room_walls, const R *Tg,
+                                           double Ts)
+{
+    const RoomDev &Rm = rooms[W.room];
+    double S4 = 0.0;
+    for (int q = Rm.w_begin; q < Rm.w_end; ++q) {
+        const WallDev &V = walls[room_walls[q]];
+        const int64_t g = (int64_t)V.off + (V.room_side == 0 ? 0 : V.nx - 1);
+        S4 += pow4(Store<R>::tref(V) + (double)Tg[g]);
+    }
+    return W.esig * (S4 - (double)W.room_walls * pow4(Ts));
+}
+
 // ----------------------------------------------------------- DF node math
 
 // Interior node update; returns (T+, P+).  r = dt/dx^2.
@@ -127,8 +147,8 @@ __device__ __forceinline__ void df_surface(R r, R s, R hT, R hM, R hL, R qinf, R
 // Applied fluxes of one side and their compensated integral (FP64).
 template <typename R>
 __device__ __forceinline__ void surface_flux(const WallDev &W, int side, double Tinf,
-                                             double Pinf, R Tn, R Tm, R Pn, R Pm, double Lv,
-                                             double dt, double *__restrict__ fw)
+                                             double Pinf, double qx, R Tn, R Tm, R Pn, R Pm,
+                                             double Lv, double dt, double *__restrict__ fw)
 {
     const double tref = Store<R>::tref(W);
     const double pref = (double)Store<R>::pref(W);
@@ -136,7 +156,8 @@ __device__ __forceinline__ void surface_flux(const WallDev &W, int side, double 
     double Ps = 0.5 * ((double)Pn + (double)Pm);
     double hM = W.hM[side];
     double g = hM * ((Pinf - pref) - Ps) + W.ginf[side];
-    double q = W.hT[side] * ((Tinf - tref) - Ts) + Lv * hM * ((Pinf - pref) - Ps) + W.qinf[side];
+    double q = W.hT[side] * ((Tinf - tref) - Ts) + Lv * hM * ((Pinf - pref) - Ps)
+             + (W.qinf[side] + qx);
     fw[side * 2 + 0] = q;
     fw[side * 2 + 1] = g;
     double s0 = fw[4 + side * 2], c0 = fw[8 + side * 2];
@@ -156,6 +177,7 @@ __global__ void __launch_bounds__(kStreamBlock)
 k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
             R *T0b, R *T1b, R *P0b, R *P1b, const uint8_t *__restrict__ lay,
             const double *__restrict__ roomT, const double *__restrict__ roomP,
+            const RoomDev *__restrict__ rooms, const int32_t *__restrict__ room_walls,
             double *__restrict__ flux, int *__restrict__ bad,
             const int64_t *__restrict__ step_base, int step_off, RunConst rc)
 {
@@ -234,13 +256,18 @@ k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
         R Pnb = side == 0 ? Pr : Pc[j - 1];
         double Tinf, Pinf;
         ambient(W, side, (double)n * rc.dt, roomT, roomP, Tinf, Pinf);
+        // radiation at t^n: incident flux, long-wave exchange on the zone side
+        double qx = incident(W, side, (double)n * rc.dt);
+        if (W.esig != 0.0 && W.room_side == side)
+            qx += longwave<R>(W, walls, rooms, room_walls, cb ? T1b : T0b,
+                              Store<R>::tref(W) + (double)Tj);
         const R Tid = (R)(Tinf - Store<R>::tref(W));
         const R Pid = (R)(Pinf - (double)pr);
         const R hM = (R)W.hM[side];
         df_surface<R>(r, (R)W.s, (R)W.hT[side], hM, (R)(rc.Lv * W.hM[side]),
-                      (R)W.qinf[side], (R)W.ginf[side], c, k, Tm, Pm, Tnb, Pnb, Tid, Pid,
-                      Tn, Pn);
-        surface_flux<R>(W, side, Tinf, Pinf, Tn, Tm, Pn, Pm, rc.Lv, rc.dt,
+                      (R)(W.qinf[side] + qx), (R)W.ginf[side], c, k, Tm, Pm, Tnb, Pnb, Tid,
+                      Pid, Tn, Pn);
+        surface_flux<R>(W, side, Tinf, Pinf, qx, Tn, Tm, Pn, Pm, rc.Lv, rc.dt,
                         flux + (int64_t)tile.x * 12);
     }
     if (!(isfinite(Tn) && isfinite(Pn))) atomicOr(bad, 1);
@@ -268,13 +295,14 @@ template <typename R>
 __global__ void __launch_bounds__(kStartBlock)
 k_startup(const WallDev *__restrict__ walls, R *T0b, R *T1b, R *P0b, R *P1b,
           const uint8_t *__restrict__ lay, const double *__restrict__ roomT,
-          const double *__restrict__ roomP, double *__restrict__ flux, int *__restrict__ bad,
-          RunConst rc)
+          const double *__restrict__ roomP, const RoomDev *__restrict__ rooms,
+          const int32_t *__restrict__ room_walls, double *__restrict__ flux,
+          int *__restrict__ bad, RunConst rc)
 {
     __shared__ double sT[kMaxNx], sP[kMaxNx], skT[kMaxNx], skM[kMaxNx], skX[kMaxNx];
     __shared__ uint8_t sl[kMaxNx];
     __shared__ double red[kStartBlock];
-    __shared__ double amb[4];
+    __shared__ double amb[6];           // per side: T_inf, P_inf, heat source
 
     const WallDev &W = walls[blockIdx.x];
     const int nx = W.nx;
@@ -335,20 +363,29 @@ k_startup(const WallDev *__restrict__ walls, R *T0b, R *T1b, R *P0b, R *P1b,
         for (int s = 0; s < 2; ++s)
             for (int f = 0; f < 2; ++f) { fs[s][f] = fw[4 + s * 2 + f]; fc[s][f] = fw[8 + s * 2 + f]; }
 
+    // long-wave exchange of the zone side, held at level 0 for the whole step
+    double qlw[2] = {0.0, 0.0};
+    if (tid == 0 && W.esig != 0.0)
+        qlw[W.room_side] = longwave<R>(W, walls, rooms, room_walls, T0b,
+                                       sT[W.room_side == 0 ? 0 : nx - 1]);
+
     double nT[kStartNpt], nP[kStartNpt];
     for (int64_t k = 0; k < m; ++k) {
         const double t = (double)k * rc.dt / (double)m;
         if (tid == 0) {
-            for (int s = 0; s < 2; ++s) ambient(W, s, t, roomT, roomP, amb[2 * s], amb[2 * s + 1]);
+            for (int s = 0; s < 2; ++s) {
+                ambient(W, s, t, roomT, roomP, amb[3 * s], amb[3 * s + 1]);
+                amb[3 * s + 2] = W.qinf[s] + (incident(W, s, t) + qlw[s]);
+            }
         }
         faces();
         __syncthreads();
         if (tid == 0) {
             for (int s = 0; s < 2; ++s) {
                 int j = s == 0 ? 0 : nx - 1;
-                double Tinf = amb[2 * s], Pinf = amb[2 * s + 1];
+                double Tinf = amb[3 * s], Pinf = amb[3 * s + 1];
                 double g = W.hM[s] * (Pinf - sP[j]) + W.ginf[s];
-                double q = W.hT[s] * (Tinf - sT[j]) + rc.Lv * W.hM[s] * (Pinf - sP[j]) + W.qinf[s];
+                double q = W.hT[s] * (Tinf - sT[j]) + rc.Lv * W.hM[s] * (Pinf - sP[j]) + amb[3 * s + 2];
                 neumaier_add(fs[s][0], fc[s][0], dts * q);
                 neumaier_add(fs[s][1], fc[s][1], dts * g);
                 acc[s][0] += q;
@@ -372,9 +409,9 @@ k_startup(const WallDev *__restrict__ walls, R *T0b, R *T1b, R *P0b, R *P1b,
             }
             if (j == 0 || j == nx - 1) {
                 int s = j == 0 ? 0 : 1;
-                double Tinf = amb[2 * s], Pinf = amb[2 * s + 1];
+                double Tinf = amb[3 * s], Pinf = amb[3 * s + 1];
                 dM += W.hM[s] * (Pinf - P) + W.ginf[s];
-                dT += W.hT[s] * (Tinf - T) + rc.Lv * W.hM[s] * (Pinf - P) + W.qinf[s];
+                dT += W.hT[s] * (Tinf - T) + rc.Lv * W.hM[s] * (Pinf - P) + amb[3 * s + 2];
             }
             double Pnew = P + dts * dM / (c.cM * width);
             double Tnew = T + (dts * dT / width - c.cX * (Pnew - P)) / c.cT;

@@ -18,10 +18,13 @@
 //
 // Per step (two workgroup barriers):
 //   A  lanes publish their first / last node (level n) and surface values;
+//      one lane per wall side publishes the ambient and the incident
+//      radiation at t^n;
 //   B  lanes read the neighbour halos, evaluate the NPT right faces at the
 //      face-averaged state (Sec. 3.1) and publish the last one; one lane per
 //      zone advances the zone air by forward Euler from the level-n surfaces
-//      (Sec. 5.3, eq. wbse_tn_exp);
+//      (Sec. 5.3, eq. wbse_tn_exp) and adds the long-wave exchange among the
+//      zone's surfaces (Sec. 2) to their heat sources;
 //   C  lanes take their first left face from LDS and update moisture, then
 //      heat (App. A, eq. DF_eq2b); surface nodes use the DF-averaged Robin
 //      half cell (eq. bc_v) with the outdoor air at t^n or the level-n zone
@@ -70,6 +73,11 @@ template <typename R> struct WallRec {
     R fk[8][4];               // per entry: k0, kM0 (layer, interface with the next, none),
                               // theta ref, Pv ref
     int32_t wstart, wend, wid, wroom, wside, pad[3];
+    // radiative sources (used by the RAD variant only)
+    double qx[2][2];          // [parity][side] heat source at t^n (incident, plus the
+                              // long-wave exchange on a zone side)
+    double rotq[2][6];        // per side: incident mean, amp, phase sin/cos, step sin/cos
+    double esig, pad_e;       // s eps sigma of the zone side
 };
 struct RoomRec {
     double air[2][2];         // [parity][T, P]
@@ -137,7 +145,9 @@ template <typename R, int NPT, int NT> constexpr int res_waves_per_eu()
     return NPT > 4 ? 2 : (sizeof(R) == 8 || NT > 256 ? 4 : 3);
 }
 
-template <typename R, int NPT, int NT>
+// RAD: the launch has radiative sources (incident flux or long-wave
+// exchange); without them the corresponding work is compiled out.
+template <typename R, int NPT, int NT, bool RAD>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT>())))
 k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ block_walls,
               const int32_t *__restrict__ block_rooms, const WallDev *__restrict__ walls,
@@ -198,6 +208,8 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             if (rr[z].rid == W.room) lr = z;
         X.wroom = lr;
         X.wside = W.room_side;
+        X.esig = W.esig;
+        X.qx[0][0] = X.qx[0][1] = X.qx[1][0] = X.qx[1][1] = 0.0;
         for (int side = 0; side < 2; ++side) {
             double *bc = X.bc[side];
             bc[0] = W.dx;                       // s / r
@@ -245,6 +257,13 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         sincos(2.0 * dpi() * t0 / SR[2] + SR[3], &st[6], &st[7]);
         sincos(2.0 * dpi() * rc.dt / ST[2], &st[8], &st[9]);
         sincos(2.0 * dpi() * rc.dt / SR[2], &st[10], &st[11]);
+        if constexpr (RAD) {
+            const double *SQ = W.qsun[amb_side];
+            double *sq = wr[amb_slot].rotq[amb_side];
+            sq[0] = SQ[0]; sq[1] = SQ[1];
+            sincos(2.0 * dpi() * t0 / SQ[2] + SQ[3], &sq[2], &sq[3]);
+            sincos(2.0 * dpi() * rc.dt / SQ[2], &sq[4], &sq[5]);
+        }
     }
 
     // ---- per-node set-up: levels, table offsets, flags
@@ -325,6 +344,14 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             }
             wr[amb_slot].amb[par][amb_side][0] = Ta;
             wr[amb_slot].amb[par][amb_side][1] = Pa;
+            if constexpr (RAD) {
+                double *sq = wr[amb_slot].rotq[amb_side];
+                const double qs = sq[0] + sq[1] * sq[2];
+                wr[amb_slot].qx[par][amb_side] = qs > 0.0 ? qs : 0.0;
+                const double sQ = sq[2], cQ = sq[3];
+                sq[2] = fma(sQ, sq[5], cQ * sq[4]);
+                sq[3] = fma(cQ, sq[5], -sQ * sq[4]);
+            }
             const double sT = st[4], cTr = st[5], sR = st[6], cR = st[7];
             st[4] = fma(sT, st[9], cTr * st[8]);
             st[5] = fma(cTr, st[9], -sT * st[8]);
@@ -352,6 +379,8 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             const double Pout = sine_at(Rm.RHout, tt) * psat_th(Tout - 273.15);
             double G = go + gv * (Pout - Pa) / Pv_ref;
             double Q = Qh + Lv * go + gv * cma * (Tout - Ta) + Lv * gv * (Pout - Pa) / Pv_ref;
+            double S4 = 0.0;            // sum of T_w^4 over the zone's surfaces
+            int m = 0;
             for (int s = 0; s < nwb; ++s) {
                 if (wr[s].wroom != t) continue;
                 const int side = wr[s].wside;
@@ -359,9 +388,17 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const double Ts = wr[s].surf[par][side][0], Ps = wr[s].surf[par][side][1];
                 G += bc[7] * bc[2] * (Ps - Pa);
                 Q += bc[7] * (bc[1] * (Ts - Ta) + bc[3] * (Ps - Pa));
+                if constexpr (RAD) { S4 += pow4(Ts); ++m; }
             }
             rr[t].air[par ^ 1][1] = Pa + dt * G / (mass / Pv_ref);
             rr[t].air[par ^ 1][0] = Ta + dt * Q / (mass * cma);
+            // long-wave exchange among the zone's surfaces (Sec. 2), level n
+            if constexpr (RAD)
+                for (int s = 0; s < nwb; ++s) {
+                    if (wr[s].wroom != t || wr[s].esig == 0.0) continue;
+                    const int side = wr[s].wside;
+                    wr[s].qx[par][side] += wr[s].esig * (S4 - (double)m * pow4(wr[s].surf[par][side][0]));
+                }
         }
         R kT[NPT], kM[NPT], phn[NPT];
 #pragma unroll
@@ -459,7 +496,8 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const R d = (R)bc[0];                      // s / r
                 const R hT = (R)bc[1], hM = (R)bc[2];
                 const R hL = (R)bc[3];
-                const R ginf = (R)bc[4], qinf = (R)bc[5];
+                const double qsrc = RAD ? bc[5] + X.qx[par][side] : bc[5];   // constant + radiative
+                const R ginf = (R)bc[4], qinf = (R)qsrc;
                 const R gM = fma((R)2, k_M, (R)2 * d * hM);     // 2 r k + 2 s h (over r)
                 const R gT = fma((R)2, k_T, (R)2 * d * hT);
                 const R gX = fma((R)2, k_X, (R)2 * d * hL);
@@ -488,7 +526,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const double Ps = 0.5 * ((double)Pnew + (double)Pm[q]);
                 const double g = bc[2] * ((Pinf - (double)pr) - Ps) + bc[4];
                 const double qh = bc[1] * ((Tinf - tref) - Ts)
-                                + bc[3] * ((Pinf - (double)pr) - Ps) + bc[5];
+                                + bc[3] * ((Pinf - (double)pr) - Ps) + qsrc;
                 double *fw = X.flux;
                 fw[side * 2] = qh;
                 fw[side * 2 + 1] = g;

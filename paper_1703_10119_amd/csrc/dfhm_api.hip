@@ -61,6 +61,7 @@ struct dfhm_ctx {
     double pack_eff = 0.0;
     int res_threads = 0, res_npt = 0;
     bool packed = false;
+    bool radiative = false;          // some wall has an incident or long-wave source
     // captured chunk of streaming steps
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -161,13 +162,18 @@ std::string check_wall(const dfhm_wall &w, int64_t i)
             snprintf(b, sizeof b, "wall %lld side %d: bad surface coefficients", (long long)i, s);
             return b;
         }
-        const dfhm_sine *ss[2] = {&w.T_amb[s], &w.RH_amb[s]};
+        const dfhm_sine *ss[3] = {&w.T_amb[s], &w.RH_amb[s], &w.q_sun[s]};
         for (const dfhm_sine *q : ss)
             if (!(std::isfinite(q->period_s) && q->period_s > 0.0) || !std::isfinite(q->mean) ||
                 !std::isfinite(q->amp) || !std::isfinite(q->phase)) {
-                snprintf(b, sizeof b, "wall %lld side %d: bad ambient sinusoid", (long long)i, s);
+                snprintf(b, sizeof b, "wall %lld side %d: bad ambient or radiation sinusoid",
+                         (long long)i, s);
                 return b;
             }
+        if (!(w.emissivity[s] >= 0.0 && w.emissivity[s] <= 1.0)) {
+            snprintf(b, sizeof b, "wall %lld side %d: emissivity outside [0, 1]", (long long)i, s);
+            return b;
+        }
     }
     if (!(std::isfinite(w.T0) && w.T0 > 0.0) || !(std::isfinite(w.RH0) && w.RH0 > 0.0) ||
         !finite_nonneg(w.area_m2)) {
@@ -196,7 +202,12 @@ void fill_wall(WallDev &d, const dfhm_wall &w, int32_t off)
         const dfhm_sine &a = w.T_amb[s], &b = w.RH_amb[s];
         d.Tamb[s][0] = a.mean; d.Tamb[s][1] = a.amp; d.Tamb[s][2] = a.period_s; d.Tamb[s][3] = a.phase;
         d.RHamb[s][0] = b.mean; d.RHamb[s][1] = b.amp; d.RHamb[s][2] = b.period_s; d.RHamb[s][3] = b.phase;
+        const dfhm_sine &q = w.q_sun[s];
+        d.qsun[s][0] = q.mean; d.qsun[s][1] = q.amp; d.qsun[s][2] = q.period_s; d.qsun[s][3] = q.phase;
+        d.emis[s] = w.emissivity[s];
     }
+    d.esig = 0.0;          // set when a zone is coupled
+    d.room_walls = 0;
     for (int l = 0; l < kMaxLayers; ++l) {
         const dfhm_layer &m = w.layer[l];
         double *p = d.lay[l];
@@ -230,8 +241,8 @@ dfhm_status launch_stream_step(dfhm_ctx *c, int off)
 {
     hipLaunchKernelGGL(k_df_stream<R>, dim3(c->ntiles), dim3(kStreamBlock), 0, c->stream,
                        c->d_walls, c->d_tiles, (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0],
-                       (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_flux, c->d_bad,
-                       c->d_step, off, c->rc);
+                       (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_rooms,
+                       c->d_room_walls, c->d_flux, c->d_bad, c->d_step, off, c->rc);
     return DFHM_OK;
 }
 
@@ -252,8 +263,8 @@ dfhm_status launch_startup(dfhm_ctx *c)
 {
     hipLaunchKernelGGL(k_startup<R>, dim3((unsigned)c->nw), dim3(kStartBlock), 0, c->stream,
                        c->d_walls, (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0],
-                       (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_flux, c->d_bad,
-                       c->rc);
+                       (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_rooms,
+                       c->d_room_walls, c->d_flux, c->d_bad, c->rc);
     return DFHM_OK;
 }
 
@@ -515,13 +526,13 @@ void refresh_io(dfhm_ctx *c)
     c->io_valid = true;
 }
 
-template <typename R, int NPT, int NT>
+template <typename R, int NPT, int NT, bool RAD>
 void launch_res(dfhm_ctx *c, int k)
 {
     refresh_io(c);
     static bool attr_set = false;   // the largest tables need more than 64 KB of LDS
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT>,
+        (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT, RAD>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)res_lds_bytes<R>(NT, kResMaxWalls, kResMaxRooms));
         attr_set = true;
@@ -529,7 +540,7 @@ void launch_res(dfhm_ctx *c, int k)
     // LDS records sized by the largest wall / zone count of a workgroup of
     // this packing (at least one of each)
     const int mw = std::max(1, c->max_wpb), mr = std::max(1, c->max_rpb);
-    hipLaunchKernelGGL((k_df_resident<R, NPT, NT>), dim3(c->n_blocks), dim3(NT),
+    hipLaunchKernelGGL((k_df_resident<R, NPT, NT, RAD>), dim3(c->n_blocks), dim3(NT),
                        res_lds_bytes<R>(NT, mw, mr), c->stream, c->d_blocks, c->d_block_walls,
                        c->d_block_rooms, c->d_walls, (const R *)c->d_T[0], (const R *)c->d_T[1],
                        (const R *)c->d_P[0], (const R *)c->d_P[1], c->d_lay, c->d_rooms,
@@ -541,7 +552,14 @@ template <typename R>
 void launch_resident(dfhm_ctx *c, int k)
 {
     const int nt = c->res_threads, npt = c->res_npt;
-#define DFHM_RES_CASE(T_, P_) if (nt == T_ && npt == P_) { launch_res<R, P_, T_>(c, k); return; }
+    // radiative sources compile into a variant of their own, so that runs
+    // without them keep the leaner step loop
+#define DFHM_RES_CASE(T_, P_)                                                        \
+    if (nt == T_ && npt == P_) {                                                     \
+        if (c->radiative) launch_res<R, P_, T_, true>(c, k);                         \
+        else launch_res<R, P_, T_, false>(c, k);                                     \
+        return;                                                                      \
+    }
     DFHM_RES_CASE(256, 4) DFHM_RES_CASE(128, 8) DFHM_RES_CASE(256, 2) DFHM_RES_CASE(512, 2)
     DFHM_RES_CASE(128, 4) DFHM_RES_CASE(512, 4) DFHM_RES_CASE(256, 8)
 #undef DFHM_RES_CASE
@@ -674,6 +692,8 @@ dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t 
     int32_t off = 0;
     for (int64_t i = 0; i < n_walls; ++i) {
         fill_wall(c->walls[i], walls[i], off);
+        for (int sd = 0; sd < 2; ++sd)    // can the clipped incident flux be nonzero?
+            if (walls[i].q_sun[sd].mean + std::fabs(walls[i].q_sun[sd].amp) > 0.0) c->radiative = true;
         for (int j0 = 0; j0 < walls[i].nx; j0 += kStreamTile) tiles.push_back(make_int2((int)i, j0));
         off += walls[i].nx;
     }
@@ -740,7 +760,8 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
         const dfhm_room &m = rooms[r];
         if (!(m.volume_m3 > 0.0) || !(m.ach_per_h >= 0.0) || !(m.T0 > 0.0) || !(m.RH0 > 0.0) ||
             m.n_sched < 1 || !(m.sched_dt_s > 0.0) || !m.g_o_kg_s || !m.Q_h_W ||
-            !(m.T_out.period_s > 0.0) || !(m.RH_out.period_s > 0.0))
+            !(m.T_out.period_s > 0.0) || !(m.RH_out.period_s > 0.0) ||
+            !(m.view_factor >= 0.0 && m.view_factor <= 1.0))
             return fail(c, DFHM_E_INVAL, "bad zone descriptor " + std::to_string(r));
         total_sched += m.n_sched;
     }
@@ -791,6 +812,7 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
         d.w_begin = (int32_t)rw.size();
         for (int32_t w : lists[r]) rw.push_back(w);
         d.w_end = (int32_t)rw.size();
+        d.view = m.view_factor;
         Ta[r] = m.T0;
         Pa[r] = m.RH0;   // converted to Pv on the device
     }
@@ -817,6 +839,13 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
         c->room_side[w] = wall_room[w] >= 0 ? room_side[w] : 1;
         c->walls[w].room = (int32_t)wall_room[w];
         c->walls[w].room_side = c->room_side[w];
+        if (wall_room[w] >= 0) {
+            // long-wave exchange factor of the zone side: s eps sigma
+            const int64_t r = wall_room[w];
+            c->walls[w].esig = rooms[r].view_factor * c->walls[w].emis[c->room_side[w]] * kSigma;
+            c->walls[w].room_walls = (int32_t)lists[r].size();
+            if (c->walls[w].esig != 0.0) c->radiative = true;
+        }
     }
     HIP_TRY(c, hipMemcpyAsync(c->d_rooms, rd.data(), sizeof(RoomDev) * n_rooms, hipMemcpyHostToDevice, c->stream));
     if (!rw.empty())

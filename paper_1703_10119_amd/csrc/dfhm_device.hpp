@@ -34,6 +34,11 @@ struct WallDev {
     double hT[2], hM[2], qinf[2], ginf[2];
     double Tamb[2][4], RHamb[2][4];    // mean, amp, period, phase
     double lay[kMaxLayers][L_COUNT];
+    double qsun[2][4];                 // incident radiation sinusoid (clipped at 0)
+    double emis[2];                    // surface emissivities
+    double esig;                       // s eps sigma of the zone side (0: no exchange)
+    int32_t room_walls;                // walls of the coupled zone (0: none)
+    int32_t pad3;
 };
 
 struct RoomDev {
@@ -42,7 +47,11 @@ struct RoomDev {
     double sched_dt;
     int32_t n_sched, sched_off;        // offset into the schedule arrays
     int32_t w_begin, w_end;            // range in the room -> wall index list
+    double view;                       // view factor between two surfaces
 };
+
+// Stefan-Boltzmann constant, W/(m2 K4).
+constexpr double kSigma = 5.670374419e-8;
 
 // Global constants of a run (kernel argument).
 struct RunConst {
@@ -64,6 +73,20 @@ __device__ __forceinline__ float psat_th(float th)
 __device__ __forceinline__ double sine_at(const double *s, double t)
 {
     return s[0] + s[1] * sin(2.0 * dpi() * t / s[2] + s[3]);
+}
+
+// Incident radiation of one side at time t (W/m2): the sinusoid clipped at 0.
+__device__ __forceinline__ double incident(const WallDev &W, int side, double t)
+{
+    const double q = sine_at(W.qsun[side], t);
+    return q > 0.0 ? q : 0.0;
+}
+
+// Fourth power of an absolute temperature (K).
+__device__ __forceinline__ double pow4(double T)
+{
+    const double T2 = T * T;
+    return T2 * T2;
 }
 
 template <typename R> struct KCoef { R kT, kM, kX; };

@@ -46,14 +46,16 @@ class Wall(C.Structure):
                 ("h_T", C.c_double * 2), ("h_M", C.c_double * 2),
                 ("q_inf", C.c_double * 2), ("g_inf", C.c_double * 2),
                 ("T_amb", Sine * 2), ("RH_amb", Sine * 2),
-                ("T0", C.c_double), ("RH0", C.c_double), ("area_m2", C.c_double)]
+                ("T0", C.c_double), ("RH0", C.c_double), ("area_m2", C.c_double),
+                ("emissivity", C.c_double * 2), ("q_sun", Sine * 2)]
 
 
 class Room(C.Structure):
     _fields_ = [("volume_m3", C.c_double), ("ach_per_h", C.c_double), ("T0", C.c_double),
                 ("RH0", C.c_double), ("T_out", Sine), ("RH_out", Sine),
                 ("n_sched", C.c_int32), ("sched_dt_s", C.c_double),
-                ("g_o_kg_s", C.POINTER(C.c_double)), ("Q_h_W", C.POINTER(C.c_double))]
+                ("g_o_kg_s", C.POINTER(C.c_double)), ("Q_h_W", C.POINTER(C.c_double)),
+                ("view_factor", C.c_double)]
 
 
 class Config(C.Structure):
@@ -193,10 +195,23 @@ def _sine(s, row):
     s.mean, s.amp, s.period_s, s.phase = (float(x) for x in row)
 
 
+def _radiation(walls: dict, W: int):
+    """Emissivities and incident sinusoids of a wall set (absent = none)."""
+    emis = walls.get("emis")
+    if emis is None:
+        emis = np.zeros((W, 2))
+    qsun = walls.get("qsun")
+    if qsun is None:
+        qsun = np.zeros((W, 2, 4))
+        qsun[..., 2] = 86400.0
+    return np.asarray(emis, np.float64), np.asarray(qsun, np.float64)
+
+
 def walls_struct(walls: dict):
     """dfhm_wall array from a workload wall set."""
     W = len(walls["nx"])
     arr = (Wall * W)()
+    emis, qsun = _radiation(walls, W)
     lay = np.asarray(walls["layer"], np.float64)
     fields = [f for f, _ in Layer._fields_]
     for w in range(W):
@@ -213,6 +228,8 @@ def walls_struct(walls: dict):
             x.g_inf[s] = float(walls["ginf"][w, s])
             _sine(x.T_amb[s], walls["Tamb"][w, s])
             _sine(x.RH_amb[s], walls["RHamb"][w, s])
+            x.emissivity[s] = float(emis[w, s])
+            _sine(x.q_sun[s], qsun[w, s])
         x.T0 = float(walls["T0"][w])
         x.RH0 = float(walls["RH0"][w])
         x.area_m2 = float(walls["area"][w])
@@ -243,6 +260,9 @@ def walls_struct_fast(walls: dict):
     put(Wall.T0.offset, walls["T0"])
     put(Wall.RH0.offset, walls["RH0"])
     put(Wall.area_m2.offset, walls["area"])
+    emis, qsun = _radiation(walls, W)
+    put(Wall.emissivity.offset, emis)
+    put(Wall.q_sun.offset, qsun.reshape(W, -1))
     return arr
 
 
@@ -326,6 +346,7 @@ class Solver:
             x.sched_dt_s = float(rooms["sched_dt"][r])
             x.g_o_kg_s = go.ctypes.data_as(C.POINTER(C.c_double))
             x.Q_h_W = qh.ctypes.data_as(C.POINTER(C.c_double))
+            x.view_factor = float(rooms["view"][r]) if "view" in rooms else 0.0
         wr = np.ascontiguousarray(walls["wall_room"], np.int64)
         rs = np.ascontiguousarray(walls["room_side"], np.int8)
         self._check(L.dfhm_room_couple(self._h, arr, R, _ptr(wr), _ptr(rs)), "dfhm_room_couple")

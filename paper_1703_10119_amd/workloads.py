@@ -207,12 +207,21 @@ def layered_batch(n_walls: int, seed: int = 303, nx_lo: int = 51,
 
 
 def building_batch(n_rooms: int, seed: int = 404, nx_lo: int = 101,
-                   nx_hi: int = 801, n_sched: int = 24, dt: float = 1.0):
+                   nx_hi: int = 801, n_sched: int = 24, dt: float = 1.0,
+                   radiation: bool = False):
     """Box rooms (2.5 m high, square floor) with 6 layered walls each.
 
     Side 0 of every wall faces the outdoor air of its room, side 1 the room.
     Hourly moisture (0-500 g/h) and heat (0-1000 W) schedules, seeded.  Nx is
     capped so that dt/dx <= DT_OVER_DX_MAX.  Returns (walls, rooms).
+
+    radiation=True adds the radiative sources of the paper's two-zone case
+    (Sec. 6.2): room-side emissivity 0.5 with one wall per room at 0.9, view
+    factor 0.2, and on the outdoor side a daily half-wave incident flux
+    (amplitude 100-600 W/m2 per wall, standing in for the orientation; the
+    paper's own series is only shown in a figure); initial wall
+    temperatures are then spread over 291-295 K so that the long-wave
+    exchange is active from the first step.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     R = int(n_rooms)
@@ -258,6 +267,13 @@ def building_batch(n_rooms: int, seed: int = 404, nx_lo: int = 101,
     )
     _sine(rooms["Tout"], 293.0, AT, DAY, pT)
     _sine(rooms["RHout"], 0.6, AR, DAY / 2, pR)
+    if radiation:
+        w["emis"][:, 1] = 0.5
+        w["emis"][::6, 1] = 0.9
+        rooms["view"][:] = 0.2
+        _sine(w["qsun"][:, 0], 0.0, rng.uniform(100.0, 600.0, W), DAY,
+              np.repeat(pT, 6) - math.pi / 2)
+        w["T0"][:] = rng.uniform(291.0, 295.0, W)
     return w, rooms
 
 

@@ -31,7 +31,8 @@ def test_struct_sizes_match_header_layout():
     # 12 doubles per layer, 4 per sinusoid; int32 pairs where declared
     assert C.sizeof(dfhm.Layer) == 12 * 8
     assert C.sizeof(dfhm.Sine) == 4 * 8
-    assert C.sizeof(dfhm.Wall) == 8 + 3 * 96 + 8 * 8 + 4 * 32 + 3 * 8
+    assert C.sizeof(dfhm.Wall) == 8 + 3 * 96 + 8 * 8 + 4 * 32 + 3 * 8 + 2 * 8 + 2 * 32
+    assert C.sizeof(dfhm.Room) == 4 * 8 + 2 * 32 + 8 + 8 + 2 * 8 + 8
     assert dfhm._LAYER_ORDER == wl.LAYER_FIELDS
 
 

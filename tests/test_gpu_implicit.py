@@ -89,3 +89,18 @@ def test_bad_configuration_is_refused():
         args.update(kw)
         with pytest.raises(dfhm.DfhmError):
             dfhm.Implicit(walls, **args)
+
+
+def test_incident_radiation_matches_oracle():
+    """Daily half-wave incident flux on side 0 (theta-weighted between t^n
+    and t^{n+1} like the outdoor air), Euler implicit and Crank-Nicolson."""
+    walls = wl.uniform_batch(6, seed=29, nx=101, L=0.1)
+    wl._sine(walls["qsun"][:, 0], -50.0, np.linspace(200.0, 700.0, 6), 7200.0, 0.4)
+    for theta in (1.0, 0.5):
+        ic = dfhm.Implicit(walls, dt=60.0, theta=theta, eta=1e-12)
+        ic.step(120)
+        for w in range(6):
+            T, P = ic.fields(w)
+            Tr, Pr, _ = oracle.implicit_run(walls, w, 60.0, wl.LV, 120, theta=theta, eta=1e-12)
+            assert rel(T, Tr) <= TOL and rel(P, Pr) <= TOL, (theta, w, rel(T, Tr), rel(P, Pr))
+        ic.close()

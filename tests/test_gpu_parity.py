@@ -135,6 +135,27 @@ def test_rooms_coupled(pname, prec, sname, sched):
     assert eTa <= TOL[prec] and ePa <= TOL[prec]
 
 
+@pytest.mark.parametrize("pname,prec", PRECS)
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_rooms_radiating(pname, prec, sname, sched):
+    """6 rooms with long-wave exchange among their surfaces (eps 0.5 / 0.9,
+    s = 0.2), daily incident radiation outside and spread initial wall
+    temperatures (exchange active from the start-up step), dt = 10 s."""
+    walls, rooms = wl.building_batch(6, seed=405, dt=10.0, radiation=True)
+    cfg = wl.default_config(dt=10.0)
+    say(f"radiating rooms 6x6 walls x8640 {pname} {sname}")
+    ref = oracle_run(walls, cfg, 8640, rooms=rooms)
+    s = dfhm.Solver(walls, cfg, rooms=rooms, precision=prec, schedule=sched, chunk=700)
+    s.step(8640)
+    s.sync()
+    compare(s, ref, prec, f"radiating rooms {pname} {sname}")
+    Ta, Pa = s.rooms()
+    Tar, Par = ref.rooms()
+    eTa, ePa = rel(Ta, Tar), rel(Pa, Par)
+    say(f"  room air: T={eTa:.2e} P={ePa:.2e}")
+    assert eTa <= TOL[prec] and ePa <= TOL[prec]
+
+
 @pytest.mark.parametrize("sname,sched", SCHEDS)
 def test_repeat_start(sname, sched):
     walls = wl.uniform_batch(8, seed=12, nx=301)
