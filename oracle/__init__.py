@@ -98,6 +98,7 @@ def lib():
         L.ref_startup_substeps.argtypes = [P, C.c_int64]
         L.ref_psat.restype = C.c_double
         L.ref_psat.argtypes = [C.c_double]
+        L.ref_set_links.argtypes = [P, P, P, P, C.c_int64]
         L.ref_implicit_run.restype = C.c_double
         L.ref_implicit_run.argtypes = [C.POINTER(_Wall), C.c_double, C.c_double,
                                        C.c_int64, C.c_double, C.c_double, P, P]
@@ -197,6 +198,11 @@ class RefSim:
                                room_arr, self.R, _ptr(self._wr), _ptr(self._rs))
         if not self._h:
             raise MemoryError("oracle create failed")
+        if rooms is not None and len(rooms.get("link_a", ())) > 0:
+            la = np.ascontiguousarray(rooms["link_a"], np.int32)
+            lb = np.ascontiguousarray(rooms["link_b"], np.int32)
+            lg = np.ascontiguousarray(rooms["link_g"], np.float64)
+            L.ref_set_links(self._h, _ptr(la), _ptr(lb), _ptr(lg), len(la))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -55,7 +55,12 @@
  *     zone-side surface temperatures of all walls of the zone.  Both are
  *     taken at t^n and level n, explicitly like the zone air; the start-up
  *     step holds the long-wave part at level 0 and re-evaluates the
- *     incident flux at every sub-step like the outdoor air.
+ *     incident flux at every sub-step like the outdoor air;
+ *   - inter-zone airflow (Sec. 5.1): a link exchanges g kg/s of dry air each
+ *     way; zone i gains g (c_j theta_j - c_i theta_i) + L_v g (w_j - w_i) of
+ *     heat and g (w_j - w_i) of vapour, with theta in degC (the enthalpy
+ *     reference at which L_v is the latent heat) and c = c_pa + c_pv w the
+ *     moist-air capacity of each zone, all at level n.
  */
 #include <math.h>
 #include <stdint.h>
@@ -224,6 +229,9 @@ typedef struct {
     double *fnow;             /* [w][side][field] applied flux of last step */
     double *fsum, *fcmp;      /* Neumaier pairs of the flux integrals */
     double *Ta, *Pa;          /* room air at level n */
+    int64_t nl;               /* inter-zone links: zones la[l], lb[l], flow lg[l] */
+    int32_t *la, *lb;
+    double *lg;
     int64_t n;
 } ref_sim;
 
@@ -234,7 +242,22 @@ void ref_destroy(ref_sim *s)
     free(s->room_side); free(s->off); free(s->lay);
     free(s->Tp); free(s->Tc); free(s->Pp); free(s->Pc);
     free(s->fnow); free(s->fsum); free(s->fcmp); free(s->Ta); free(s->Pa);
+    free(s->la); free(s->lb); free(s->lg);
     free(s);
+}
+
+/* Air exchanged between zones (Sec. 5.1, the inter-zone sources): link l
+ * moves lg[l] kg/s of dry air from zone la[l] to zone lb[l] and the same back.
+ * Replaces any previous links. */
+int ref_set_links(ref_sim *s, const int32_t *a, const int32_t *b, const double *g, int64_t n)
+{
+    free(s->la); free(s->lb); free(s->lg);
+    s->nl = n;
+    s->la = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    s->lb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    s->lg = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t l = 0; l < n; ++l) { s->la[l] = a[l]; s->lb[l] = b[l]; s->lg[l] = g[l]; }
+    return 0;
 }
 
 ref_sim *ref_create(const ref_cfg *cfg, const ref_wall *walls, int64_t nw,
@@ -540,7 +563,8 @@ static double longwave(const ref_sim *s, int64_t w)
 
 /* Room air at step n -> n+1 by forward Euler (eq. LAV_equation with
  * w ~ Pv / Pv_ref, exchange terms eq. LAV_couplage at the level-n wall
- * surface values, sources at t^n). */
+ * surface values, inter-zone airflow at the level-n air of the linked
+ * zones, sources at t^n). */
 static void room_step(const ref_sim *s, int64_t r, double t, double *Ta_new,
                       double *Pa_new)
 {
@@ -565,6 +589,20 @@ static void room_step(const ref_sim *s, int64_t r, double t, double *Ta_new,
         double Ts = s->Tc[j], Ps = s->Pc[j];
         G += wl->area * wl->hM[side] * (Ps - Pa);
         Q += wl->area * (wl->hT[side] * (Ts - Ta) + c->Lv * wl->hM[side] * (Ps - Pa));
+    }
+    /* inter-zone airflow from each linked zone j (level n): the moist-air
+     * enthalpy c_j theta_j - c_i theta_i (theta in degC, c = c_pa + c_pv w) and
+     * the latent part L_v (w_j - w_i) */
+    for (int64_t l = 0; l < s->nl; ++l) {
+        int64_t j;
+        if (s->la[l] == r) j = s->lb[l];
+        else if (s->lb[l] == r) j = s->la[l];
+        else continue;
+        double g = s->lg[l];
+        double Tj = s->Ta[j], Pj = s->Pa[j];
+        double cj = c->c_pa + c->c_pv * Pj / c->Pv_ref;
+        G += g * (Pj - Pa) / c->Pv_ref;
+        Q += g * (cj * (Tj - 273.15) - cma * (Ta - 273.15)) + c->Lv * g * (Pj - Pa) / c->Pv_ref;
     }
     *Pa_new = Pa + c->dt * G / (mass / c->Pv_ref);
     *Ta_new = Ta + c->dt * Q / (mass * cma);

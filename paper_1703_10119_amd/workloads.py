@@ -24,7 +24,8 @@ A wall set is a dict of arrays (W walls, 3 layer slots):
 A room set is a dict:  volume, ach, T0, RH0 [R]; Tout, RHout [R, 4];
 sched_dt [R]; g_o, Q_h [R, S] (kg/s and W, periodic piecewise constant);
 view [R] (view factor between two surfaces of the room; 0 = no long-wave
-exchange).
+exchange); optionally link_a, link_b [L] int32 and link_g [L] f64 (kg/s of
+dry air exchanged each way between two rooms).
 """
 from __future__ import annotations
 
