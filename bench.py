@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--rooms", type=int, default=4096)
     ap.add_argument("--radiation", action="store_true",
                     help="building workload with the radiative surface sources")
+    ap.add_argument("--link-group", type=int, default=1,
+                    help="building workload: rooms linked by airflow in chains of this many")
     ap.add_argument("--shape", default=None,
                     help="resident launch shape THREADSxNODES (e.g. 256x4); default: the library's")
     ap.add_argument("--dt", type=float, default=None)
@@ -200,11 +202,14 @@ def other_workload(a, torch, dfhm, wl):
                 f"capped at dt/dx <= 3333 s/m), dt = {dt:g} s")
     else:
         dt = a.dt or 10.0
-        walls, rooms = wl.building_batch(a.rooms, seed=404, dt=dt, radiation=a.radiation)
+        walls, rooms = wl.building_batch(a.rooms, seed=404, dt=dt, radiation=a.radiation,
+                                         link_group=a.link_group)
         name = (f"building batch: {a.rooms} rooms x 6 layered walls (Nx 101-801, capped), "
                 f"room-air balance every step, dt = {dt:g} s"
                 + (", long-wave exchange among each room's surfaces and incident radiation"
-                   if a.radiation else ""))
+                   if a.radiation else "")
+                + (f", rooms linked in chains of {a.link_group} (0.3 h^-1 airflow)"
+                   if a.link_group > 1 else ""))
     cfg = wl.default_config(dt=dt)
     cells = int(wl.total_nodes(walls))
     out = {"metric": "DF cell-updates/s", "unit": "cell-updates/s", "n_gpus": 1,

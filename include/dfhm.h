@@ -160,7 +160,8 @@ dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t 
                         void *arena, size_t arena_bytes, dfhm_ctx **out);
 
 /* Couple walls to n_rooms zones (Sec. 5.1-5.3): wall_room[w] = zone index or
- * -1, room_side[w] = 0 | 1 the side facing that zone.  Each step the walls
+ * -1, room_side[w] = 0 | 1 the side facing that zone; every zone needs at
+ * least one wall (DFHM_E_INVAL otherwise).  Each step the walls
  * see the zone air of level n on that side and the zone is advanced by
  * forward Euler with the level-n surface values (eq. wbse_tn_exp).  Allowed
  * only at step index 0, once.  DFHM_E_UNSTABLE if a zone's explicit step
@@ -168,6 +169,29 @@ dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t 
  * (rho_a V c_ma) and a_M = (sum A h_M + g_v / Pv_ref) Pv_ref / (rho_a V). */
 dfhm_status dfhm_room_couple(dfhm_ctx *ctx, const dfhm_room *rooms, int64_t n_rooms,
                              const int64_t *wall_room, const int8_t *room_side);
+
+/* Airflow between two zones (Sec. 5.1, the inter-zone sources of eq.
+ * LAV_equation): g_kg_s of dry air moves from zone_a to zone_b and the same
+ * back.  Zone i gains the heat g (c_j theta_j - c_i theta_i) + L_v g (w_j - w_i)
+ * and the vapour g (w_j - w_i) from its partner j, with theta = T - 273.15
+ * (degC: the moist-air enthalpy c_pa theta + w (L_v + c_pv theta) of the
+ * two zones), c = c_pa + c_pv w and w = Pv / Pv_ref, all at level n. */
+typedef struct {
+    int32_t zone_a, zone_b;         /* distinct zone indices */
+    double g_kg_s;                  /* >= 0 */
+} dfhm_zone_link;
+
+/* Link zones (host array of n_links >= 1 links, copied).  Allowed once, after
+ * dfhm_room_couple, at step index 0.  The zone stability test of
+ * dfhm_room_couple is repeated with the link flows added to both zones'
+ * g_v (DFHM_E_UNSTABLE).  The resident schedule keeps linked zones, with all
+ * their walls, in one workgroup: a connected set of zones must fit one
+ * (at most 16 zones, 64 walls, the launch shape's node capacity and 8 links
+ * per zone), else stepping on that schedule fails with DFHM_E_INVAL and the
+ * streaming schedule is the one to use.  Errors: DFHM_E_INVAL (zone index out
+ * of range, zone_a == zone_b, g < 0 or not finite, no zones coupled),
+ * DFHM_E_STATE (not at step 0, or links set before). */
+dfhm_status dfhm_zone_links(dfhm_ctx *ctx, const dfhm_zone_link *links, int64_t n_links);
 
 /* Queue n_steps >= 0 time steps (asynchronous on the context stream). */
 dfhm_status dfhm_step_n(dfhm_ctx *ctx, int64_t n_steps);
@@ -204,6 +228,8 @@ typedef struct {
     int32_t chunk_steps, n_blocks, max_walls_per_block, use_graph;
     int64_t n_walls, n_rooms, total_nodes, step_index;
     double pack_efficiency;   /* useful nodes / node slots of the resident packing */
+    int32_t max_rooms_per_block, reserved;
+    int64_t n_links;          /* inter-zone links */
 } dfhm_info;
 dfhm_status dfhm_get_info(const dfhm_ctx *ctx, dfhm_info *info);
 

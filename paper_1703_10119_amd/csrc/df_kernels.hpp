@@ -441,14 +441,40 @@ k_startup(const WallDev *__restrict__ walls, R *T0b, R *T1b, R *P0b, R *P1b,
 
 // ------------------------------------------------------------------ rooms
 
+// One lane per zone: heat and vapour it gains from its linked zones (Sec.
+// 5.1, inter-zone sources) at the level-n air, into inz[2 r], inz[2 r + 1];
+// runs before k_room_step, which updates the air in place.
+__global__ void __launch_bounds__(64)
+k_zone_exchange(const RoomDev *__restrict__ rooms, const ZoneLinkDev *__restrict__ links,
+                const double *__restrict__ roomT, const double *__restrict__ roomP,
+                double *__restrict__ inz, int nr, RunConst rc)
+{
+    const int rix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rix >= nr) return;
+    const RoomDev &Rm = rooms[rix];
+    const double Ta = roomT[rix], Pa = roomP[rix];
+    const double cma = rc.c_pa + rc.c_pv * Pa / rc.Pv_ref;
+    double Q = 0.0, G = 0.0;
+    for (int l = Rm.l_begin; l < Rm.l_end; ++l) {
+        const ZoneLinkDev L = links[l];
+        const double Tj = roomT[L.partner], Pj = roomP[L.partner];
+        const double cj = rc.c_pa + rc.c_pv * Pj / rc.Pv_ref;
+        G += L.g * (Pj - Pa) / rc.Pv_ref;
+        Q += L.g * (cj * (Tj - 273.15) - cma * (Ta - 273.15)) + rc.Lv * L.g * (Pj - Pa) / rc.Pv_ref;
+    }
+    inz[2 * rix] = Q;
+    inz[2 * rix + 1] = G;
+}
+
 // One lane per zone: forward Euler of the zone balance with the level-n
-// surface values of its walls (ascending wall order), sources at t^n.
+// surface values of its walls (ascending wall order), sources at t^n and,
+// when inz is given, the inter-zone gains of k_zone_exchange.
 template <typename R>
 __global__ void __launch_bounds__(64)
 k_room_step(const RoomDev *__restrict__ rooms, const int32_t *__restrict__ room_walls,
             const WallDev *__restrict__ walls, const R *T0b, const R *T1b, const R *P0b,
             const R *P1b, double *roomT, double *roomP, const double *__restrict__ sched_go,
-            const double *__restrict__ sched_qh, int nr,
+            const double *__restrict__ sched_qh, const double *__restrict__ inz, int nr,
             const int64_t *__restrict__ step_base, int step_off, RunConst rc)
 {
     const int rix = blockIdx.x * blockDim.x + threadIdx.x;
@@ -477,6 +503,10 @@ k_room_step(const RoomDev *__restrict__ rooms, const int32_t *__restrict__ room_
         const double Ps = (double)Store<R>::pref(W) + (double)Pc[g];
         G += W.area * W.hM[side] * (Ps - Pa);
         Q += W.area * (W.hT[side] * (Ts - Ta) + rc.Lv * W.hM[side] * (Ps - Pa));
+    }
+    if (inz) {
+        Q += inz[2 * rix];
+        G += inz[2 * rix + 1];
     }
     roomP[rix] = Pa + rc.dt * G / (mass / rc.Pv_ref);
     roomT[rix] = Ta + rc.dt * Q / (mass * cma);

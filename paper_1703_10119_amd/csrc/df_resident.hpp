@@ -45,6 +45,7 @@ namespace dfhm {
 
 constexpr int kResMaxWalls = 64;   // walls per workgroup (LDS tables)
 constexpr int kResMaxRooms = 16;   // zones per workgroup
+constexpr int kResMaxLinks = 8;    // inter-zone links per zone
 
 struct ResBlock {
     int32_t w_begin, w_end;        // range in block_walls (ascending wall ids)
@@ -73,15 +74,21 @@ template <typename R> struct WallRec {
     R fk[8][4];               // per entry: k0, kM0 (layer, interface with the next, none),
                               // theta ref, Pv ref
     int32_t wstart, wend, wid, wroom, wside, pad[3];
-    // radiative sources (used by the RAD variant only)
+};
+// A wall's radiative sources (extended variant only, in LDS after the wall
+// records, so that the other variants keep the smaller footprint).
+struct RadRec {
     double qx[2][2];          // [parity][side] heat source at t^n (incident, plus the
                               // long-wave exchange on a zone side)
     double rotq[2][6];        // per side: incident mean, amp, phase sin/cos, step sin/cos
-    double esig, pad_e;       // s eps sigma of the zone side
+    double esig, pad;         // s eps sigma of the zone side
 };
 struct RoomRec {
     double air[2][2];         // [parity][T, P]
-    int32_t rid, pad[3];
+    double lg[kResMaxLinks];  // inter-zone links: flow (kg/s) and the partner's slot
+    int32_t lslot[kResMaxLinks];
+    int32_t rid, nlink, nwall, pad;
+    uint8_t wslot[kResMaxWalls];   // slots of the zone's walls (ascending)
 };
 // Pointers the kernel needs only after its step loop (read from device
 // memory there, so that they do not occupy scalar registers through the loop).
@@ -103,9 +110,11 @@ template <typename R> __host__ __device__ constexpr size_t res_off_walls(int nt)
 {
     return res_off_rc<R>(nt) + 64;
 }
-template <typename R> __host__ __device__ constexpr size_t res_lds_bytes(int nt, int mw, int mr)
+template <typename R> __host__ __device__ constexpr size_t res_lds_bytes(int nt, int mw, int mr,
+                                                                        bool ext)
 {
-    return res_off_walls<R>(nt) + sizeof(WallRec<R>) * (size_t)mw + sizeof(RoomRec) * (size_t)mr;
+    return res_off_walls<R>(nt) + (sizeof(WallRec<R>) + (ext ? sizeof(RadRec) : 0)) * (size_t)mw +
+           sizeof(RoomRec) * (size_t)mr;
 }
 
 // Keeps the scheduler from interleaving the nodes of a lane (bounds the
@@ -145,9 +154,12 @@ template <typename R, int NPT, int NT> constexpr int res_waves_per_eu()
     return NPT > 4 ? 2 : (sizeof(R) == 8 || NT > 256 ? 4 : 3);
 }
 
-// RAD: the launch has radiative sources (incident flux or long-wave
-// exchange); without them the corresponding work is compiled out.
-template <typename R, int NPT, int NT, bool RAD>
+// Kernel variants: only what a launch needs is compiled in, since every
+// extra line of the step loop competes for the registers of the node work.
+constexpr int kModePlain = 0;   // walls without zones or radiative sources
+constexpr int kModeZones = 1;   // zones coupled to walls
+constexpr int kModeExt = 2;     // radiative sources and / or linked zones
+template <typename R, int NPT, int NT, int MODE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT>())))
 k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ block_walls,
               const int32_t *__restrict__ block_rooms, const WallDev *__restrict__ walls,
@@ -155,11 +167,14 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
               const uint8_t *__restrict__ lay, const RoomDev *__restrict__ rooms,
               const double *roomT, const double *roomP, const double *__restrict__ sched_go,
               const double *__restrict__ sched_qh, const double *flux,
-              const int64_t *__restrict__ step_base, const ResIO *__restrict__ io, int ksteps,
-              int mw, RunConst rc, Shape sh)
+              const int64_t *__restrict__ step_base, const ResIO *__restrict__ io,
+              const ZoneLinkDev *__restrict__ zlinks, int ksteps, int mw, RunConst rc, Shape sh)
 {
     static_assert(NT >= 2 * kResMaxWalls, "one lane per wall side computes the ambient");
-    static_assert(sizeof(WallRec<R>) % 16 == 0, "records keep 16-byte alignment");
+    constexpr bool ZON = MODE != kModePlain, EXT = MODE == kModeExt;
+    static_assert(sizeof(WallRec<R>) % 16 == 0 && sizeof(RoomRec) % 16 == 0 &&
+                      sizeof(RadRec) % 16 == 0,
+                  "records keep 16-byte alignment");
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int nthreads = NT;
     constexpr size_t kRc = res_off_rc<R>(NT), kWalls = res_off_walls<R>(NT);
@@ -167,7 +182,9 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     R *facb = halo + 4 * NT;                             // [2][NT]
     double *s_rc = (double *)(lds + kRc);                // dt, Lv, rho_a, c_pa, c_pv, Pv_ref
     WallRec<R> *wr = (WallRec<R> *)(lds + kWalls);
-    RoomRec *rr = (RoomRec *)(lds + kWalls + sizeof(WallRec<R>) * (size_t)mw);
+    RadRec *xr = (RadRec *)(lds + kWalls + sizeof(WallRec<R>) * (size_t)mw);   // EXT only
+    RoomRec *rr = (RoomRec *)(lds + kWalls + (sizeof(WallRec<R>) + (EXT ? sizeof(RadRec) : 0)) *
+                                                 (size_t)mw);
 
     const int t = threadIdx.x;
     const ResBlock B = blocks[blockIdx.x];
@@ -188,7 +205,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             wr[s].wend = acc;
         }
     }
-    if (t < nrb) {
+    if (ZON && t < nrb) {
         int r = block_rooms[B.r_begin + t];
         rr[t].rid = r;
         rr[t].air[n0 & 1][0] = roomT[r];
@@ -208,8 +225,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             if (rr[z].rid == W.room) lr = z;
         X.wroom = lr;
         X.wside = W.room_side;
-        X.esig = W.esig;
-        X.qx[0][0] = X.qx[0][1] = X.qx[1][0] = X.qx[1][1] = 0.0;
+        if constexpr (EXT) {
+            xr[t].esig = W.esig;
+            xr[t].qx[0][0] = xr[t].qx[0][1] = xr[t].qx[1][0] = xr[t].qx[1][1] = 0.0;
+        }
         for (int side = 0; side < 2; ++side) {
             double *bc = X.bc[side];
             bc[0] = W.dx;                       // s / r
@@ -242,6 +261,30 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         X.fk[kFaceNone][0] = X.fk[kFaceNone][1] = (R)0;
         X.fk[7][0] = X.fk[7][1] = (R)0;
     }
+    // each zone's wall slots, and its inter-zone links: partner zones sit in
+    // this workgroup (the packer keeps linked zones together); resolve them to
+    // local slots
+    if (ZON && t < nrb) {
+        int nwz = 0;
+        for (int s = 0; s < nwb; ++s)
+            if (walls[wr[s].wid].room == rr[t].rid) rr[t].wslot[nwz++] = (uint8_t)s;
+        rr[t].nwall = nwz;
+        rr[t].nlink = 0;
+        if constexpr (EXT) {
+            const RoomDev &Rm = rooms[rr[t].rid];
+            int nl = 0;
+            for (int l = Rm.l_begin; l < Rm.l_end && nl < kResMaxLinks; ++l) {
+                const ZoneLinkDev L = zlinks[l];
+                for (int z = 0; z < nrb; ++z)
+                    if (rr[z].rid == L.partner) {
+                        rr[t].lslot[nl] = z;
+                        rr[t].lg[nl] = L.g;
+                        ++nl;
+                    }
+            }
+            rr[t].nlink = nl;
+        }
+    }
 
     // ---- ambient lanes: one per wall side; the outdoor sinusoids advance by
     // an exact rotation through the chunk, anchored at t^n0 (state in LDS)
@@ -257,9 +300,9 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         sincos(2.0 * dpi() * t0 / SR[2] + SR[3], &st[6], &st[7]);
         sincos(2.0 * dpi() * rc.dt / ST[2], &st[8], &st[9]);
         sincos(2.0 * dpi() * rc.dt / SR[2], &st[10], &st[11]);
-        if constexpr (RAD) {
+        if constexpr (EXT) {
             const double *SQ = W.qsun[amb_side];
-            double *sq = wr[amb_slot].rotq[amb_side];
+            double *sq = xr[amb_slot].rotq[amb_side];
             sq[0] = SQ[0]; sq[1] = SQ[1];
             sincos(2.0 * dpi() * t0 / SQ[2] + SQ[3], &sq[2], &sq[3]);
             sincos(2.0 * dpi() * rc.dt / SQ[2], &sq[4], &sq[5]);
@@ -320,7 +363,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         halo[nthreads + t] = Pn[0];
         halo[2 * nthreads + t] = Tn[NPT - 1];
         halo[3 * nthreads + t] = Pn[NPT - 1];
-        if (nrb > 0) {
+        if (ZON && nrb > 0) {
 #pragma unroll
             for (int q = 0; q < NPT; ++q) {
                 const int f = info[q];
@@ -335,7 +378,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         if (amb_lane) {
             double Ta, Pa;
             double *st = wr[amb_slot].rot[amb_side];
-            if (amb_zone >= 0) {
+            if (ZON && amb_zone >= 0) {
                 Ta = rr[amb_zone].air[par][0];
                 Pa = rr[amb_zone].air[par][1];
             } else {
@@ -344,10 +387,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             }
             wr[amb_slot].amb[par][amb_side][0] = Ta;
             wr[amb_slot].amb[par][amb_side][1] = Pa;
-            if constexpr (RAD) {
-                double *sq = wr[amb_slot].rotq[amb_side];
+            if constexpr (EXT) {
+                double *sq = xr[amb_slot].rotq[amb_side];
                 const double qs = sq[0] + sq[1] * sq[2];
-                wr[amb_slot].qx[par][amb_side] = qs > 0.0 ? qs : 0.0;
+                xr[amb_slot].qx[par][amb_side] = qs > 0.0 ? qs : 0.0;
                 const double sQ = sq[2], cQ = sq[3];
                 sq[2] = fma(sQ, sq[5], cQ * sq[4]);
                 sq[3] = fma(cQ, sq[5], -sQ * sq[4]);
@@ -364,7 +407,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         const R Pr_nb = t + 1 < nthreads ? halo[nthreads + t + 1] : (R)0;
         const R Tl_nb = t > 0 ? halo[2 * nthreads + t - 1] : (R)0;
         const R Pl_nb = t > 0 ? halo[3 * nthreads + t - 1] : (R)0;
-        if (t < nrb) {
+        if (ZON && t < nrb) {
             const double dt = s_rc[0], Lv = s_rc[1], rho_a = s_rc[2], c_pa = s_rc[3];
             const double c_pv = s_rc[4], Pv_ref = s_rc[5];
             const RoomDev &Rm = rooms[rr[t].rid];
@@ -380,24 +423,36 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             double G = go + gv * (Pout - Pa) / Pv_ref;
             double Q = Qh + Lv * go + gv * cma * (Tout - Ta) + Lv * gv * (Pout - Pa) / Pv_ref;
             double S4 = 0.0;            // sum of T_w^4 over the zone's surfaces
-            int m = 0;
-            for (int s = 0; s < nwb; ++s) {
-                if (wr[s].wroom != t) continue;
+            const int m = rr[t].nwall;
+            for (int k = 0; k < m; ++k) {
+                const int s = rr[t].wslot[k];
                 const int side = wr[s].wside;
                 const double *bc = wr[s].bc[side];
                 const double Ts = wr[s].surf[par][side][0], Ps = wr[s].surf[par][side][1];
                 G += bc[7] * bc[2] * (Ps - Pa);
                 Q += bc[7] * (bc[1] * (Ts - Ta) + bc[3] * (Ps - Pa));
-                if constexpr (RAD) { S4 += pow4(Ts); ++m; }
+                if constexpr (EXT) S4 += pow4(Ts);
             }
+            // airflow from the linked zones (Sec. 5.1, inter-zone sources):
+            // moist-air enthalpy with theta in degC, level-n air
+            if constexpr (EXT)
+                for (int l = 0; l < rr[t].nlink; ++l) {
+                    const RoomRec &J = rr[rr[t].lslot[l]];
+                    const double g = rr[t].lg[l];
+                    const double Tj = J.air[par][0], Pj = J.air[par][1];
+                    const double cj = c_pa + c_pv * Pj / Pv_ref;
+                    G += g * (Pj - Pa) / Pv_ref;
+                    Q += g * (cj * (Tj - 273.15) - cma * (Ta - 273.15)) + Lv * g * (Pj - Pa) / Pv_ref;
+                }
             rr[t].air[par ^ 1][1] = Pa + dt * G / (mass / Pv_ref);
             rr[t].air[par ^ 1][0] = Ta + dt * Q / (mass * cma);
             // long-wave exchange among the zone's surfaces (Sec. 2), level n
-            if constexpr (RAD)
-                for (int s = 0; s < nwb; ++s) {
-                    if (wr[s].wroom != t || wr[s].esig == 0.0) continue;
+            if constexpr (EXT)
+                for (int k = 0; k < m; ++k) {
+                    const int s = rr[t].wslot[k];
+                    if (xr[s].esig == 0.0) continue;
                     const int side = wr[s].wside;
-                    wr[s].qx[par][side] += wr[s].esig * (S4 - (double)m * pow4(wr[s].surf[par][side][0]));
+                    xr[s].qx[par][side] += xr[s].esig * (S4 - (double)m * pow4(wr[s].surf[par][side][0]));
                 }
         }
         R kT[NPT], kM[NPT], phn[NPT];
@@ -496,7 +551,8 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const R d = (R)bc[0];                      // s / r
                 const R hT = (R)bc[1], hM = (R)bc[2];
                 const R hL = (R)bc[3];
-                const double qsrc = RAD ? bc[5] + X.qx[par][side] : bc[5];   // constant + radiative
+                double qsrc = bc[5];                          // constant + radiative
+                if constexpr (EXT) qsrc += xr[s].qx[par][side];
                 const R ginf = (R)bc[4], qinf = (R)qsrc;
                 const R gM = fma((R)2, k_M, (R)2 * d * hM);     // 2 r k + 2 s h (over r)
                 const R gT = fma((R)2, k_T, (R)2 * d * hT);
@@ -586,7 +642,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         int s = q / 12, k = q % 12;
         O.flux[(int64_t)wr[s].wid * 12 + k] = wr[s].flux[k];
     }
-    if (t < nrb) {
+    if (ZON && t < nrb) {
         O.roomT[rr[t].rid] = rr[t].air[nend & 1][0];
         O.roomP[rr[t].rid] = rr[t].air[nend & 1][1];
     }

@@ -61,7 +61,17 @@ struct dfhm_ctx {
     double pack_eff = 0.0;
     int res_threads = 0, res_npt = 0;
     bool packed = false;
-    bool radiative = false;          // some wall has an incident or long-wave source
+    // some wall has an incident or long-wave source, or zones are linked: the
+    // resident kernel then runs its extended variant
+    bool extended = false;
+    // inter-zone links
+    void *link_mem = nullptr;
+    ZoneLinkDev *d_links = nullptr;   // per receiving zone (RoomDev l_begin..l_end)
+    double *d_inz = nullptr;          // per zone: heat, vapour gained (streaming)
+    int64_t n_links = 0;
+    std::vector<RoomDev> rooms_host;
+    std::vector<std::vector<int32_t>> zone_partners;   // linked zones of each zone
+    std::vector<double> zone_mass, zone_cma, zone_sT, zone_sM;   // stability sums
     // captured chunk of streaming steps
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -251,10 +261,14 @@ dfhm_status launch_room_step(dfhm_ctx *c, int off)
 {
     if (c->nr == 0) return DFHM_OK;
     int nb = (int)((c->nr + 63) / 64);
+    if (c->n_links > 0)
+        hipLaunchKernelGGL(k_zone_exchange, dim3(nb), dim3(64), 0, c->stream, c->d_rooms,
+                           c->d_links, c->d_roomT, c->d_roomP, c->d_inz, (int)c->nr, c->rc);
     hipLaunchKernelGGL(k_room_step<R>, dim3(nb), dim3(64), 0, c->stream, c->d_rooms,
                        c->d_room_walls, c->d_walls, (const R *)c->d_T[0], (const R *)c->d_T[1],
                        (const R *)c->d_P[0], (const R *)c->d_P[1], c->d_roomT, c->d_roomP,
-                       c->d_go, c->d_qh, (int)c->nr, c->d_step, off, c->rc);
+                       c->d_go, c->d_qh, c->n_links > 0 ? c->d_inz : nullptr, (int)c->nr,
+                       c->d_step, off, c->rc);
     return DFHM_OK;
 }
 
@@ -349,35 +363,58 @@ int effective_schedule(const dfhm_ctx *c)
     return c->shape_uniform ? DFHM_SCHED_RESIDENT : DFHM_SCHED_STREAM;
 }
 
-// Groups that must share a workgroup: a zone with all of its walls, or one
-// wall.  Returns the largest group size in nodes and in walls.
-void groups_of(const dfhm_ctx *c, std::vector<std::vector<int32_t>> &groups)
+// Groups that must share a workgroup: a set of linked zones with all of
+// their walls, or one wall without a zone (walls and zones ascending).
+struct Group {
+    std::vector<int32_t> walls, rooms;
+};
+void groups_of(const dfhm_ctx *c, std::vector<Group> &groups)
 {
     groups.clear();
-    std::vector<int64_t> first(c->nr, -1);
+    std::vector<int64_t> root(c->nr);
+    for (int64_t r = 0; r < c->nr; ++r) root[r] = r;
+    auto find = [&](int64_t x) {
+        while (root[x] != x) { root[x] = root[root[x]]; x = root[x]; }
+        return x;
+    };
+    for (int64_t r = 0; r < (int64_t)c->zone_partners.size(); ++r)
+        for (int32_t p : c->zone_partners[r]) {
+            int64_t a = find(r), b = find(p);
+            if (a != b) root[std::max(a, b)] = std::min(a, b);
+        }
+    std::vector<int64_t> gid(c->nr, -1);
     for (int64_t w = 0; w < c->nw; ++w) {
         int64_t r = c->wall_room[w];
-        if (r < 0) { groups.push_back({(int32_t)w}); continue; }
-        if (first[r] < 0) { first[r] = (int64_t)groups.size(); groups.push_back({}); }
-        groups[first[r]].push_back((int32_t)w);
+        if (r < 0) { groups.push_back({{(int32_t)w}, {}}); continue; }
+        int64_t z = find(r);
+        if (gid[z] < 0) { gid[z] = (int64_t)groups.size(); groups.push_back({}); }
+        groups[gid[z]].walls.push_back((int32_t)w);
     }
+    for (int64_t r = 0; r < c->nr; ++r) groups[gid[find(r)]].rooms.push_back((int32_t)r);
 }
 
 dfhm_status pack(dfhm_ctx *c, int nt, int npt)
 {
     const int cap = nt * npt;
-    std::vector<std::vector<int32_t>> groups;
+    std::vector<Group> groups;
     groups_of(c, groups);
     std::vector<int> gsize(groups.size());
     for (size_t g = 0; g < groups.size(); ++g) {
         int s = 0;
-        for (int32_t w : groups[g]) s += c->walls[w].nx;
+        for (int32_t w : groups[g].walls) s += c->walls[w].nx;
         gsize[g] = s;
         if (s > cap)
             return fail(c, DFHM_E_INVAL, "a wall or zone group of " + std::to_string(s) +
                                              " nodes exceeds the workgroup capacity " + std::to_string(cap));
-        if ((int)groups[g].size() > kResMaxWalls)
-            return fail(c, DFHM_E_INVAL, "a zone has more walls than a workgroup holds");
+        if ((int)groups[g].walls.size() > kResMaxWalls)
+            return fail(c, DFHM_E_INVAL, "a zone group has more walls than a workgroup holds");
+        if ((int)groups[g].rooms.size() > kResMaxRooms)
+            return fail(c, DFHM_E_INVAL, "a set of linked zones has more zones than a workgroup holds");
+        for (int32_t r : groups[g].rooms)
+            if ((int)c->zone_partners[r].size() > kResMaxLinks)
+                return fail(c, DFHM_E_INVAL, "zone " + std::to_string(r) + " has more than " +
+                                                 std::to_string(kResMaxLinks) +
+                                                 " links (resident schedule)");
     }
     std::vector<int> order(groups.size());
     for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
@@ -388,8 +425,8 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
     std::multimap<int, int> free_cap;   // remaining -> bin
     for (int g : order) {
         const int need = gsize[g];
-        const int gw = (int)groups[g].size();
-        const int gr = c->wall_room[groups[g][0]] >= 0 ? 1 : 0;
+        const int gw = (int)groups[g].walls.size();
+        const int gr = (int)groups[g].rooms.size();
         int chosen = -1;
         for (auto it = free_cap.lower_bound(need); it != free_cap.end(); ++it) {
             Bin &b = bins[it->second];
@@ -417,9 +454,8 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
         std::vector<int32_t> ws;
         std::vector<int32_t> rs;
         for (int g : bins[i].gs) {
-            for (int32_t w : groups[g]) ws.push_back(w);
-            int64_t r = c->wall_room[groups[g][0]];
-            if (r >= 0) rs.push_back((int32_t)r);
+            for (int32_t w : groups[g].walls) ws.push_back(w);
+            for (int32_t r : groups[g].rooms) rs.push_back(r);
         }
         std::sort(ws.begin(), ws.end());
         std::sort(rs.begin(), rs.end());
@@ -467,12 +503,12 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
 
 int max_group(const dfhm_ctx *c)
 {
-    std::vector<std::vector<int32_t>> groups;
+    std::vector<Group> groups;
     groups_of(c, groups);
     int m = 0;
     for (auto &g : groups) {
         int s = 0;
-        for (int32_t w : g) s += c->walls[w].nx;
+        for (int32_t w : g.walls) s += c->walls[w].nx;
         m = std::max(m, s);
     }
     return m;
@@ -526,38 +562,42 @@ void refresh_io(dfhm_ctx *c)
     c->io_valid = true;
 }
 
-template <typename R, int NPT, int NT, bool RAD>
+template <typename R, int NPT, int NT, int MODE>
 void launch_res(dfhm_ctx *c, int k)
 {
     refresh_io(c);
     static bool attr_set = false;   // the largest tables need more than 64 KB of LDS
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT, RAD>,
+        (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT, MODE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)res_lds_bytes<R>(NT, kResMaxWalls, kResMaxRooms));
+                                  (int)res_lds_bytes<R>(NT, kResMaxWalls, kResMaxRooms,
+                                                        MODE == kModeExt));
         attr_set = true;
     }
     // LDS records sized by the largest wall / zone count of a workgroup of
     // this packing (at least one of each)
     const int mw = std::max(1, c->max_wpb), mr = std::max(1, c->max_rpb);
-    hipLaunchKernelGGL((k_df_resident<R, NPT, NT, RAD>), dim3(c->n_blocks), dim3(NT),
-                       res_lds_bytes<R>(NT, mw, mr), c->stream, c->d_blocks, c->d_block_walls,
+    hipLaunchKernelGGL((k_df_resident<R, NPT, NT, MODE>), dim3(c->n_blocks), dim3(NT),
+                       res_lds_bytes<R>(NT, mw, mr, MODE == kModeExt), c->stream, c->d_blocks,
+                       c->d_block_walls,
                        c->d_block_rooms, c->d_walls, (const R *)c->d_T[0], (const R *)c->d_T[1],
                        (const R *)c->d_P[0], (const R *)c->d_P[1], c->d_lay, c->d_rooms,
-                       c->d_roomT, c->d_roomP, c->d_go, c->d_qh, c->d_flux, c->d_step, c->d_io, k,
-                       mw, c->rc, c->shape);
+                       c->d_roomT, c->d_roomP, c->d_go, c->d_qh, c->d_flux, c->d_step, c->d_io,
+                       c->d_links, k, mw, c->rc, c->shape);
 }
 
 template <typename R>
 void launch_resident(dfhm_ctx *c, int k)
 {
     const int nt = c->res_threads, npt = c->res_npt;
-    // radiative sources compile into a variant of their own, so that runs
-    // without them keep the leaner step loop
+    // zones and radiative sources / links compile into variants of their
+    // own, so that runs without them keep the leaner step loop
+    const int mode = c->extended ? kModeExt : (c->nr > 0 ? kModeZones : kModePlain);
 #define DFHM_RES_CASE(T_, P_)                                                        \
     if (nt == T_ && npt == P_) {                                                     \
-        if (c->radiative) launch_res<R, P_, T_, true>(c, k);                         \
-        else launch_res<R, P_, T_, false>(c, k);                                     \
+        if (mode == kModeExt) launch_res<R, P_, T_, kModeExt>(c, k);                 \
+        else if (mode == kModeZones) launch_res<R, P_, T_, kModeZones>(c, k);        \
+        else launch_res<R, P_, T_, kModePlain>(c, k);                                \
         return;                                                                      \
     }
     DFHM_RES_CASE(256, 4) DFHM_RES_CASE(128, 8) DFHM_RES_CASE(256, 2) DFHM_RES_CASE(512, 2)
@@ -693,7 +733,7 @@ dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t 
     for (int64_t i = 0; i < n_walls; ++i) {
         fill_wall(c->walls[i], walls[i], off);
         for (int sd = 0; sd < 2; ++sd)    // can the clipped incident flux be nonzero?
-            if (walls[i].q_sun[sd].mean + std::fabs(walls[i].q_sun[sd].amp) > 0.0) c->radiative = true;
+            if (walls[i].q_sun[sd].mean + std::fabs(walls[i].q_sun[sd].amp) > 0.0) c->extended = true;
         for (int j0 = 0; j0 < walls[i].nx; j0 += kStreamTile) tiles.push_back(make_int2((int)i, j0));
         off += walls[i].nx;
     }
@@ -742,6 +782,26 @@ dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t 
     return DFHM_OK;
 }
 
+namespace {
+// Forward Euler of zone r is stable and monotone when a dt < 1 for both
+// fields, a = (sum of its exchange conductances) / (its capacity).
+dfhm_status zone_stable(dfhm_ctx *c, int64_t r, double sT = -1.0, double sM = -1.0)
+{
+    if (sT < 0.0) sT = c->zone_sT[r];
+    if (sM < 0.0) sM = c->zone_sM[r];
+    const RunConst &rc = c->rc;
+    const double aT = sT / (c->zone_mass[r] * c->zone_cma[r]);
+    const double aM = sM / (c->zone_mass[r] / rc.Pv_ref);
+    if (!(aT * rc.dt < 1.0) || !(aM * rc.dt < 1.0)) {
+        char b[200];
+        snprintf(b, sizeof b, "zone %lld: explicit step unstable (a_T dt = %.3g, a_M dt = %.3g)",
+                 (long long)r, aT * rc.dt, aM * rc.dt);
+        return fail(c, DFHM_E_UNSTABLE, b);
+    }
+    return DFHM_OK;
+}
+} // namespace
+
 dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_rooms,
                              const int64_t *wall_room, const int8_t *room_side)
 {
@@ -769,8 +829,14 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
     std::vector<std::vector<int32_t>> lists(n_rooms);
     for (int64_t w = 0; w < c->nw; ++w)
         if (wall_room[w] >= 0) lists[wall_room[w]].push_back((int32_t)w);
+    for (int64_t r = 0; r < n_rooms; ++r)
+        if (lists[r].empty()) return fail(c, DFHM_E_INVAL, "zone " + std::to_string(r) + " has no wall");
     // explicit zone step stability (forward Euler): a dt < 1 for both fields
     const RunConst &rc = c->rc;
+    c->zone_mass.assign(n_rooms, 0.0);
+    c->zone_cma.assign(n_rooms, 0.0);
+    c->zone_sT.assign(n_rooms, 0.0);
+    c->zone_sM.assign(n_rooms, 0.0);
     for (int64_t r = 0; r < n_rooms; ++r) {
         const dfhm_room &m = rooms[r];
         double mass = rc.rho_a * m.volume_m3;
@@ -784,13 +850,9 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
             sT += W.area * W.hT[side];
             sM += W.area * W.hM[side];
         }
-        double aT = sT / (mass * cma), aM = sM / (mass / rc.Pv_ref);
-        if (!(aT * rc.dt < 1.0) || !(aM * rc.dt < 1.0)) {
-            char b[200];
-            snprintf(b, sizeof b, "zone %lld: explicit step unstable (a_T dt = %.3g, a_M dt = %.3g)",
-                     (long long)r, aT * rc.dt, aM * rc.dt);
-            return fail(c, DFHM_E_UNSTABLE, b);
-        }
+        c->zone_mass[r] = mass; c->zone_cma[r] = cma; c->zone_sT[r] = sT; c->zone_sM[r] = sM;
+        dfhm_status st = zone_stable(c, r);
+        if (st) return st;
     }
     std::vector<RoomDev> rd(n_rooms);
     std::vector<int32_t> rw;
@@ -813,6 +875,7 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
         for (int32_t w : lists[r]) rw.push_back(w);
         d.w_end = (int32_t)rw.size();
         d.view = m.view_factor;
+        d.l_begin = d.l_end = 0;
         Ta[r] = m.T0;
         Pa[r] = m.RH0;   // converted to Pv on the device
     }
@@ -844,7 +907,7 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
             const int64_t r = wall_room[w];
             c->walls[w].esig = rooms[r].view_factor * c->walls[w].emis[c->room_side[w]] * kSigma;
             c->walls[w].room_walls = (int32_t)lists[r].size();
-            if (c->walls[w].esig != 0.0) c->radiative = true;
+            if (c->walls[w].esig != 0.0) c->extended = true;
         }
     }
     HIP_TRY(c, hipMemcpyAsync(c->d_rooms, rd.data(), sizeof(RoomDev) * n_rooms, hipMemcpyHostToDevice, c->stream));
@@ -860,7 +923,69 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->nr = n_rooms;
+    c->rooms_host = rd;
+    c->zone_partners.assign(n_rooms, {});
     c->packed = false;   // the resident packing must keep zones whole
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_zone_links(dfhm_ctx *c, const dfhm_zone_link *links, int64_t n_links)
+{
+    if (!c) return DFHM_E_INVAL;
+    if (c->nr == 0) return fail(c, DFHM_E_INVAL, "no zones are coupled");
+    if (c->n != 0 || c->n_links != 0) return fail(c, DFHM_E_STATE, "zones are linked once, at step 0");
+    if (!links || n_links < 1) return fail(c, DFHM_E_INVAL, "links are required");
+    for (int64_t l = 0; l < n_links; ++l) {
+        const dfhm_zone_link &k = links[l];
+        if (k.zone_a < 0 || k.zone_a >= c->nr || k.zone_b < 0 || k.zone_b >= c->nr ||
+            k.zone_a == k.zone_b || !(std::isfinite(k.g_kg_s) && k.g_kg_s >= 0.0))
+            return fail(c, DFHM_E_INVAL, "bad zone link " + std::to_string(l));
+    }
+    // stability with the link flows added to both zones (zone i loses
+    // g c_i to its temperature and g / Pv_ref to its humidity ratio)
+    std::vector<double> sT = c->zone_sT, sM = c->zone_sM;
+    for (int64_t l = 0; l < n_links; ++l)
+        for (int32_t z : {links[l].zone_a, links[l].zone_b}) {
+            sT[z] += links[l].g_kg_s * c->zone_cma[z];
+            sM[z] += links[l].g_kg_s / c->rc.Pv_ref;
+        }
+    for (int64_t r = 0; r < c->nr; ++r) {
+        dfhm_status st = zone_stable(c, r, sT[r], sM[r]);
+        if (st) return st;
+    }
+    // per receiving zone, in link order
+    std::vector<std::vector<ZoneLinkDev>> per(c->nr);
+    for (int64_t l = 0; l < n_links; ++l) {
+        const dfhm_zone_link &k = links[l];
+        per[k.zone_a].push_back({k.zone_b, 0, k.g_kg_s});
+        per[k.zone_b].push_back({k.zone_a, 0, k.g_kg_s});
+    }
+    std::vector<ZoneLinkDev> flat;
+    std::vector<RoomDev> rd = c->rooms_host;
+    for (int64_t r = 0; r < c->nr; ++r) {
+        rd[r].l_begin = (int32_t)flat.size();
+        for (const ZoneLinkDev &d : per[r]) {
+            flat.push_back(d);
+            c->zone_partners[r].push_back(d.partner);
+        }
+        rd[r].l_end = (int32_t)flat.size();
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    size_t o_l = take(sizeof(ZoneLinkDev) * flat.size());
+    size_t o_x = take(sizeof(double) * 2 * c->nr);
+    void *mem = nullptr;
+    if (hipMalloc(&mem, o) != hipSuccess) return fail(c, DFHM_E_NOMEM, "zone links");
+    c->link_mem = mem;
+    c->d_links = (ZoneLinkDev *)((char *)mem + o_l);
+    c->d_inz = (double *)((char *)mem + o_x);
+    HIP_TRY(c, hipMemcpyAsync(c->d_links, flat.data(), sizeof(ZoneLinkDev) * flat.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_rooms, rd.data(), sizeof(RoomDev) * c->nr, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->rooms_host = rd;
+    c->n_links = n_links;
+    c->extended = true;
+    c->packed = false;   // linked zones share a workgroup
     return DFHM_OK;
 }
 
@@ -1027,6 +1152,9 @@ dfhm_status dfhm_get_info(const dfhm_ctx *c, dfhm_info *info)
                                                : (sched == DFHM_SCHED_RESIDENT ? 1000 : 100);
     info->n_blocks = sched == DFHM_SCHED_RESIDENT ? c->n_blocks : c->ntiles;
     info->max_walls_per_block = c->max_wpb;
+    info->max_rooms_per_block = c->max_rpb;
+    info->reserved = 0;
+    info->n_links = c->n_links;
     info->use_graph = c->cfg.use_graph;
     info->n_walls = c->nw;
     info->n_rooms = c->nr;
@@ -1201,6 +1329,8 @@ uint64_t describe(const dfhm_ctx *c)
     }
     mix(c->wall_room.data(), sizeof(int64_t) * c->wall_room.size());
     mix(&c->nr, sizeof c->nr);
+    for (const auto &p : c->zone_partners)       // linked zones (none: nothing mixed)
+        if (!p.empty()) mix(p.data(), sizeof(int32_t) * p.size());
     return h;
 }
 
@@ -1297,6 +1427,7 @@ void dfhm_destroy(dfhm_ctx *c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->own_arena && c->arena) (void)hipFree(c->arena);
     if (c->room_mem) (void)hipFree(c->room_mem);
+    if (c->link_mem) (void)hipFree(c->link_mem);
     if (c->pack_mem) (void)hipFree(c->pack_mem);
     delete c;
 }

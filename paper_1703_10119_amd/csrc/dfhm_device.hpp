@@ -48,6 +48,13 @@ struct RoomDev {
     int32_t n_sched, sched_off;        // offset into the schedule arrays
     int32_t w_begin, w_end;            // range in the room -> wall index list
     double view;                       // view factor between two surfaces
+    int32_t l_begin, l_end;            // range in the zone-link table
+};
+
+// One direction of an inter-zone link, listed under the receiving zone.
+struct ZoneLinkDev {
+    int32_t partner, pad;
+    double g;                          // kg/s of dry air each way
 };
 
 // Stefan-Boltzmann constant, W/(m2 K4).

@@ -73,7 +73,9 @@ class Info(C.Structure):
                 ("chunk_steps", C.c_int32), ("n_blocks", C.c_int32),
                 ("max_walls_per_block", C.c_int32), ("use_graph", C.c_int32),
                 ("n_walls", C.c_int64), ("n_rooms", C.c_int64), ("total_nodes", C.c_int64),
-                ("step_index", C.c_int64), ("pack_efficiency", C.c_double)]
+                ("step_index", C.c_int64), ("pack_efficiency", C.c_double),
+                ("max_rooms_per_block", C.c_int32), ("reserved", C.c_int32),
+                ("n_links", C.c_int64)]
 
 
 class ImplicitConfig(C.Structure):
@@ -98,7 +100,12 @@ class FeatureDesc(C.Structure):
                 ("RH_scale", C.c_float), ("p_mean", C.c_float * 8), ("p_scale", C.c_float * 8)]
 
 
-EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_step_n", "dfhm_sync",
+class ZoneLink(C.Structure):
+    _fields_ = [("zone_a", C.c_int32), ("zone_b", C.c_int32), ("g_kg_s", C.c_double)]
+
+
+EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_zone_links",
+           "dfhm_step_n", "dfhm_sync",
            "dfhm_fluxes", "dfhm_get_fields", "dfhm_get_all_fields", "dfhm_set_fields",
            "dfhm_set_step_index", "dfhm_get_rooms", "dfhm_get_info", "dfhm_autotune",
            "dfhm_step_index", "dfhm_last_error", "dfhm_status_string", "dfhm_destroy",
@@ -127,6 +134,7 @@ def load(path: str = LIB_PATH):
     L.dfhm_create.argtypes = [C.POINTER(Config), C.POINTER(Wall), I64, P, C.c_size_t,
                               C.POINTER(P)]
     L.dfhm_room_couple.argtypes = [P, C.POINTER(Room), I64, P, P]
+    L.dfhm_zone_links.argtypes = [P, C.POINTER(ZoneLink), I64]
     L.dfhm_step_n.argtypes = [P, I64]
     L.dfhm_sync.argtypes = [P]
     L.dfhm_fluxes.argtypes = [P, P, P]
@@ -145,7 +153,8 @@ def load(path: str = LIB_PATH):
     L.dfhm_status_string.argtypes = [C.c_int]
     L.dfhm_destroy.restype = None
     L.dfhm_destroy.argtypes = [P]
-    for f in (L.dfhm_create, L.dfhm_room_couple, L.dfhm_step_n, L.dfhm_sync, L.dfhm_fluxes,
+    for f in (L.dfhm_create, L.dfhm_room_couple, L.dfhm_zone_links, L.dfhm_step_n,
+              L.dfhm_sync, L.dfhm_fluxes,
               L.dfhm_get_fields, L.dfhm_get_all_fields, L.dfhm_set_fields,
               L.dfhm_set_step_index, L.dfhm_get_rooms, L.dfhm_get_info, L.dfhm_autotune):
         f.restype = C.c_int
@@ -350,7 +359,17 @@ class Solver:
         wr = np.ascontiguousarray(walls["wall_room"], np.int64)
         rs = np.ascontiguousarray(walls["room_side"], np.int8)
         self._check(L.dfhm_room_couple(self._h, arr, R, _ptr(wr), _ptr(rs)), "dfhm_room_couple")
+        if len(rooms.get("link_a", ())) > 0:
+            self.link_zones(rooms["link_a"], rooms["link_b"], rooms["link_g"])
         self.R = R
+
+    def link_zones(self, a, b, g):
+        """dfhm_zone_links: g[l] kg/s of dry air each way between zones a[l], b[l]."""
+        n = len(a)
+        arr = (ZoneLink * n)()
+        for l in range(n):
+            arr[l].zone_a, arr[l].zone_b, arr[l].g_kg_s = int(a[l]), int(b[l]), float(g[l])
+        self._check(load().dfhm_zone_links(self._h, arr, n), "dfhm_zone_links")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -209,7 +209,7 @@ def layered_batch(n_walls: int, seed: int = 303, nx_lo: int = 51,
 
 def building_batch(n_rooms: int, seed: int = 404, nx_lo: int = 101,
                    nx_hi: int = 801, n_sched: int = 24, dt: float = 1.0,
-                   radiation: bool = False):
+                   radiation: bool = False, link_group: int = 1):
     """Box rooms (2.5 m high, square floor) with 6 layered walls each.
 
     Side 0 of every wall faces the outdoor air of its room, side 1 the room.
@@ -223,6 +223,11 @@ def building_batch(n_rooms: int, seed: int = 404, nx_lo: int = 101,
     paper's own series is only shown in a figure); initial wall
     temperatures are then spread over 291-295 K so that the long-wave
     exchange is active from the first step.
+
+    link_group = k > 1 joins consecutive rooms into chains of k zones
+    (0-1-...-(k-1), k-...) with an airflow of 0.3 air changes per hour of the
+    smaller zone each way (the inter-zone flow of the paper's two-zone case,
+    Sec. 6.2, is 0.3 h^-1).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     R = int(n_rooms)
@@ -275,6 +280,11 @@ def building_batch(n_rooms: int, seed: int = 404, nx_lo: int = 101,
         _sine(w["qsun"][:, 0], 0.0, rng.uniform(100.0, 600.0, W), DAY,
               np.repeat(pT, 6) - math.pi / 2)
         w["T0"][:] = rng.uniform(291.0, 295.0, W)
+    if link_group > 1:
+        a = [r for r in range(R - 1) if (r + 1) % link_group != 0]
+        rooms["link_a"] = np.array(a, np.int32)
+        rooms["link_b"] = np.array([r + 1 for r in a], np.int32)
+        rooms["link_g"] = 0.3 * 1.2 * np.minimum(volume[a], volume[[r + 1 for r in a]]) / 3600.0
     return w, rooms
 
 

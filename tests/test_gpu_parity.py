@@ -156,6 +156,64 @@ def test_rooms_radiating(pname, prec, sname, sched):
     assert eTa <= TOL[prec] and ePa <= TOL[prec]
 
 
+@pytest.mark.parametrize("pname,prec", PRECS)
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+@pytest.mark.parametrize("group,radiation", [(2, True), (4, False)])
+def test_rooms_linked(pname, prec, sname, sched, group, radiation):
+    """Airflow between zones (0.3 h^-1 of the smaller zone): 8 rooms as
+    two-zone buildings with radiation (the paper's Sec. 6.2 combination), or
+    as chains of four zones (one workgroup per chain on the resident
+    schedule); dt = 10 s, one day."""
+    walls, rooms = wl.building_batch(8, seed=406, dt=10.0, nx_lo=51, nx_hi=301,
+                                     radiation=radiation, link_group=group)
+    cfg = wl.default_config(dt=10.0)
+    say(f"linked rooms (groups of {group}, radiation {radiation}) x8640 {pname} {sname}")
+    ref = oracle_run(walls, cfg, 8640, rooms=rooms)
+    s = dfhm.Solver(walls, cfg, rooms=rooms, precision=prec, schedule=sched, chunk=900)
+    s.step(8640)
+    s.sync()
+    compare(s, ref, prec, f"linked rooms {group} {pname} {sname}")
+    Ta, Pa = s.rooms()
+    Tar, Par = ref.rooms()
+    eTa, ePa = rel(Ta, Tar), rel(Pa, Par)
+    say(f"  room air: T={eTa:.2e} P={ePa:.2e}")
+    assert eTa <= TOL[prec] and ePa <= TOL[prec]
+    if sched == dfhm.SCHED_RESIDENT:
+        assert s.info()["max_rooms_per_block"] >= group
+
+
+def test_zone_link_errors_and_resident_capacity():
+    walls, rooms = wl.building_batch(10, seed=7, dt=10.0, nx_lo=21, nx_hi=41)
+    cfg = wl.default_config(dt=10.0)
+    s = dfhm.Solver(walls, cfg, rooms=rooms)
+    for a, b, g in ((0, 10, 0.01), (3, 3, 0.01), (0, 1, -1.0), (0, 1, float("nan"))):
+        with pytest.raises(dfhm.DfhmError):
+            s.link_zones([a], [b], [g])
+    s.close()
+    # a star of 9 links at zone 0 exceeds the resident schedule's 8 per zone;
+    # the streaming schedule steps it and matches the oracle
+    star = dict(rooms, link_a=np.zeros(9, np.int32), link_b=np.arange(1, 10, dtype=np.int32),
+                link_g=np.full(9, 0.002))
+    r = dfhm.Solver(walls, cfg, rooms=star, schedule=dfhm.SCHED_RESIDENT)
+    with pytest.raises(dfhm.DfhmError):
+        r.step(5)
+    r.close()
+    st = dfhm.Solver(walls, cfg, rooms=star, schedule=dfhm.SCHED_STREAM)
+    st.step(300)
+    st.sync()
+    ref = oracle_run(walls, cfg, 300, rooms=star)
+    compare(st, ref, dfhm.FP64, "star of 9 links, streaming")
+    # links after the first step are refused
+    with pytest.raises(dfhm.DfhmError):
+        st.link_zones([1], [2], [0.01])
+    st.close()
+    # a flow that makes the zone step unstable is refused
+    u = dfhm.Solver(walls, cfg, rooms=rooms)
+    with pytest.raises(dfhm.DfhmError):
+        u.link_zones([0], [1], [1e3])
+    u.close()
+
+
 @pytest.mark.parametrize("sname,sched", SCHEDS)
 def test_repeat_start(sname, sched):
     walls = wl.uniform_batch(8, seed=12, nx=301)
