@@ -172,7 +172,9 @@ __device__ __forceinline__ void surface_flux(const WallDev &W, int side, double 
 
 // ------------------------------------------------------ streaming DF step
 
-template <typename R>
+// EXT: radiative sources present in the batch (incident flux or long-wave
+// exchange); without them the surface lanes skip that code entirely.
+template <typename R, bool EXT>
 __global__ void __launch_bounds__(kStreamBlock)
 k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
             R *T0b, R *T1b, R *P0b, R *P1b, const uint8_t *__restrict__ lay,
@@ -257,10 +259,13 @@ k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
         double Tinf, Pinf;
         ambient(W, side, (double)n * rc.dt, roomT, roomP, Tinf, Pinf);
         // radiation at t^n: incident flux, long-wave exchange on the zone side
-        double qx = incident(W, side, (double)n * rc.dt);
-        if (W.esig != 0.0 && W.room_side == side)
-            qx += longwave<R>(W, walls, rooms, room_walls, cb ? T1b : T0b,
-                              Store<R>::tref(W) + (double)Tj);
+        double qx = 0.0;
+        if constexpr (EXT) {
+            qx = incident(W, side, (double)n * rc.dt);
+            if (W.esig != 0.0 && W.room_side == side)
+                qx += longwave<R>(W, walls, rooms, room_walls, cb ? T1b : T0b,
+                                  Store<R>::tref(W) + (double)Tj);
+        }
         const R Tid = (R)(Tinf - Store<R>::tref(W));
         const R Pid = (R)(Pinf - (double)pr);
         const R hM = (R)W.hM[side];

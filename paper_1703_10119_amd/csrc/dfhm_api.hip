@@ -249,7 +249,8 @@ dfhm_status check_bad(dfhm_ctx *c)
 template <typename R>
 dfhm_status launch_stream_step(dfhm_ctx *c, int off)
 {
-    hipLaunchKernelGGL(k_df_stream<R>, dim3(c->ntiles), dim3(kStreamBlock), 0, c->stream,
+    auto kern = c->extended ? k_df_stream<R, true> : k_df_stream<R, false>;
+    hipLaunchKernelGGL(kern, dim3(c->ntiles), dim3(kStreamBlock), 0, c->stream,
                        c->d_walls, c->d_tiles, (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0],
                        (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_rooms,
                        c->d_room_walls, c->d_flux, c->d_bad, c->d_step, off, c->rc);

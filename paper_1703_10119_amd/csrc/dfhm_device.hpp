@@ -85,6 +85,7 @@ __device__ __forceinline__ double sine_at(const double *s, double t)
 // Incident radiation of one side at time t (W/m2): the sinusoid clipped at 0.
 __device__ __forceinline__ double incident(const WallDev &W, int side, double t)
 {
+    if (!(W.qsun[side][0] + fabs(W.qsun[side][1]) > 0.0)) return 0.0;   // never positive
     const double q = sine_at(W.qsun[side], t);
     return q > 0.0 ? q : 0.0;
 }
