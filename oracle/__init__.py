@@ -51,7 +51,8 @@ class _Wall(C.Structure):
                 ("qinf", C.c_double * 2), ("ginf", C.c_double * 2),
                 ("Tamb", _Sine * 2), ("RHamb", _Sine * 2),
                 ("T0", C.c_double), ("RH0", C.c_double), ("area", C.c_double),
-                ("emis", C.c_double * 2), ("qsun", _Sine * 2)]
+                ("emis", C.c_double * 2), ("qsun", _Sine * 2),
+                ("law", C.c_int32), ("pad_law", C.c_int32), ("Lv", C.c_double), ("cw", C.c_double)]
 
 
 class _Room(C.Structure):
@@ -65,7 +66,7 @@ class _Room(C.Structure):
 class _Cfg(C.Structure):
     _fields_ = [("dt", C.c_double), ("Lv", C.c_double), ("cw", C.c_double),
                 ("rho_a", C.c_double), ("c_pa", C.c_double), ("c_pv", C.c_double),
-                ("Pv_ref", C.c_double), ("startup", C.c_int32)]
+                ("Pv_ref", C.c_double), ("startup", C.c_int32), ("law", C.c_int32)]
 
 
 _lib = None
@@ -151,6 +152,7 @@ def _cfg_struct(cfg: dict):
     for n in ("dt", "Lv", "cw", "rho_a", "c_pa", "c_pv", "Pv_ref"):
         setattr(c, n, float(cfg[n]))
     c.startup = int(cfg.get("startup", 0))
+    c.law = int(cfg.get("law", 0))
     return c
 
 

@@ -88,6 +88,8 @@ typedef struct {
     double T0, RH0, area;
     double emis[2];       /* emissivity of each surface (zone side only) */
     ref_sine qsun[2];     /* incident radiation, clipped at zero */
+    int32_t law, pad_law; /* material law (set from the run's configuration) */
+    double Lv, cw;        /* latent heat and water heat capacity (likewise) */
 } ref_wall;
 
 typedef struct {
@@ -103,6 +105,7 @@ typedef struct {
 typedef struct {
     double dt, Lv, cw, rho_a, c_pa, c_pv, Pv_ref;
     int32_t startup; /* 0 = forward-Euler sub-steps, 1 = repeat initial level */
+    int32_t law;     /* 0 = shape law (scales x shape factors), 1 = Table 1 */
 } ref_cfg;
 
 /* ------------------------------------------------------------------ laws */
@@ -117,21 +120,100 @@ double ref_psat(double T)
 typedef struct { double kTT, kM, kTM; } ref_kcoef;
 typedef struct { double cTT, cM, cTM; } ref_ccoef;
 
-static ref_kcoef law_k(const ref_layer *m, double T, double P)
+/*
+ * Table 1 (Sec. 6, the load-bearing material), read as follows:
+ *   suction s = -P_c = -R_v T ln(phi) in J/kg (Kelvin's law with rho_l
+ *   dropped, natural log: the printed c_M formula omits rho_l and carries
+ *   the same c_1, c_2); s = 0 for phi >= 1;
+ *   moisture content f = sum_i w_i [1 + (c_i s)^n_i]^(-m_i), (w, c, n) =
+ *   (47.1, 1.25e-5, 1.65) and (109.9, 1.8e-5, 6), m_i = 1 - 1/n_i (the
+ *   printed 0.39 and 0.83, and the printed c_M prefactors 30.62 = 47.1 m_1
+ *   n_1 and 549.5 = 109.9 m_2 n_2);
+ *   c_M = (df/dphi) / P_s (Sec. 2), the derivative taken exactly;
+ *   c_TT = rho_0 c_0 + c_w f, rho_0 c_0 = 790 x 870; c_TM = c_w theta c_M;
+ *   k_TT = lambda = 0.2 + 0.0045 f;
+ *   delta_v = 1.88e-6 / T (1 - f/157) / (0.503 (1 - f/157)^2 + 0.497);
+ *   k_TM = L_v delta_v;
+ *   k_M = 1.97e-10 10^(1.44 - 0.07 log10(2 phi)) + 1.77e-7 exp(-8 (2 phi - 2)^2):
+ *   the table's moisture transfer coefficient with its first exponential
+ *   read in base 10 (its argument is a log10) and the square of the second
+ *   inside the exponent.
+ * Evaluated at 20 degC this reproduces every coefficient of Table 2 within
+ * 1.5 % for the north and east/west walls (15 % and 50 % relative
+ * humidity) and for the south wall at 75 %.
+ * A layer's k0, kM0, c0 and cM0 multiply lambda, (k_M, k_TM), rho_0 c_0 and
+ * (c_M, c_TM); 1 gives the paper's material.
+ */
+#define T1_RV 461.5
+#define T1_RHO0C0 (790.0 * 870.0)
+
+static double t1_suction(double T, double phi)
+{
+    double s = -T1_RV * T * log(phi);
+    return s > 0.0 ? s : 0.0;
+}
+
+/* moisture content f (kg/m3) and df/dphi at (T, phi) */
+static void t1_isotherm(double T, double phi, double *f, double *dfdphi)
+{
+    static const double w[2] = {47.1, 109.9}, c[2] = {1.25e-5, 1.8e-5}, n[2] = {1.65, 6.0};
+    double s = t1_suction(T, phi);
+    double F = 0.0, G = 0.0;      /* G = -df/ds */
+    for (int i = 0; i < 2; ++i) {
+        double m = 1.0 - 1.0 / n[i];
+        double x = c[i] * s;
+        double xn = pow(x, n[i]);
+        F += w[i] * pow(1.0 + xn, -m);
+        G += w[i] * m * n[i] * c[i] * pow(x, n[i] - 1.0) * pow(1.0 + xn, -m - 1.0);
+    }
+    *f = F;
+    *dfdphi = G * T1_RV * T / phi;    /* ds/dphi = -R_v T / phi */
+}
+
+static double t1_delta_v(double T, double f)
+{
+    double u = 1.0 - f / 157.0;
+    return 1.88e-6 / T * u / (0.503 * u * u + 0.497);
+}
+
+static double t1_moisture_k(double phi)
+{
+    double a = 2.0 * phi;
+    return 1.97e-10 * pow(10.0, 1.44 - 0.07 * log10(a)) + 1.77e-7 * exp(-8.0 * (a - 2.0) * (a - 2.0));
+}
+
+static ref_kcoef law_k(const ref_wall *w, const ref_layer *m, double T, double P)
 {
     ref_kcoef k;
     double phi = P / ref_psat(T);
+    if (w->law == 1) {
+        double f, df;
+        t1_isotherm(T, phi, &f, &df);
+        double dv = t1_delta_v(T, f);
+        k.kTT = m->k0 * (0.2 + 0.0045 * f);
+        k.kM = m->kM0 * t1_moisture_k(phi);
+        k.kTM = m->kM0 * w->Lv * dv;
+        return k;
+    }
     k.kTT = m->k0 * (1.0 + m->aT * phi);
     k.kM = m->kM0 * (1.0 + m->aM * phi * phi);
     k.kTM = m->bTM * k.kM;
     return k;
 }
 
-static ref_ccoef law_c(const ref_layer *m, double T, double P)
+static ref_ccoef law_c(const ref_wall *w, const ref_layer *m, double T, double P)
 {
     ref_ccoef c;
     double phi = P / ref_psat(T);
     double th = T - 273.15;
+    if (w->law == 1) {
+        double f, df;
+        t1_isotherm(T, phi, &f, &df);
+        c.cTT = m->c0 * T1_RHO0C0 + w->cw * f;
+        c.cM = m->cM0 * df / ref_psat(T);
+        c.cTM = w->cw * th * c.cM;
+        return c;
+    }
     c.cTT = m->c0 * (1.0 + m->cT * phi);
     c.cM = m->cM0 * (1.0 + m->aC * phi);
     c.cTM = (m->eTM + m->fTM * th) * c.cM;
@@ -153,9 +235,9 @@ static ref_kcoef face_k(const ref_wall *w, const int *lay, const double *T,
 {
     double Tf = 0.5 * (T[j] + T[j + 1]);
     double Pf = 0.5 * (P[j] + P[j + 1]);
-    ref_kcoef a = law_k(&w->layer[lay[j]], Tf, Pf);
+    ref_kcoef a = law_k(w, &w->layer[lay[j]], Tf, Pf);
     if (lay[j] == lay[j + 1]) return a;
-    ref_kcoef b = law_k(&w->layer[lay[j + 1]], Tf, Pf);
+    ref_kcoef b = law_k(w, &w->layer[lay[j + 1]], Tf, Pf);
     ref_kcoef k;
     k.kTT = harm(a.kTT, b.kTT);
     k.kM = harm(a.kM, b.kM);
@@ -271,6 +353,11 @@ ref_sim *ref_create(const ref_cfg *cfg, const ref_wall *walls, int64_t nw,
     s->nr = nr;
     s->walls = (ref_wall *)malloc(sizeof(ref_wall) * (size_t)(nw > 0 ? nw : 1));
     memcpy(s->walls, walls, sizeof(ref_wall) * (size_t)nw);
+    for (int64_t w = 0; w < nw; ++w) {
+        s->walls[w].law = cfg->law;
+        s->walls[w].Lv = cfg->Lv;
+        s->walls[w].cw = cfg->cw;
+    }
     s->off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nw + 1));
     s->off[0] = 0;
     for (int64_t w = 0; w < nw; ++w) s->off[w + 1] = s->off[w] + walls[w].nx;
@@ -374,7 +461,7 @@ static void df_wall_step(const ref_wall *w, const int *lay, double dt, double Lv
 
     /* moisture first */
     for (int j = 0; j < nx; ++j) {
-        ref_ccoef c = law_c(&w->layer[lay[j]], Tc[j], Pc[j]);
+        ref_ccoef c = law_c(w, &w->layer[lay[j]], Tc[j], Pc[j]);
         if (j > 0 && j < nx - 1) {
             double KM = kf[j - 1].kM + kf[j].kM;
             Pn[j] = ((c.cM - r * KM) * Pp[j]
@@ -393,7 +480,7 @@ static void df_wall_step(const ref_wall *w, const int *lay, double dt, double Lv
     }
     /* then heat, using the new vapour pressure */
     for (int j = 0; j < nx; ++j) {
-        ref_ccoef c = law_c(&w->layer[lay[j]], Tc[j], Pc[j]);
+        ref_ccoef c = law_c(w, &w->layer[lay[j]], Tc[j], Pc[j]);
         if (j > 0 && j < nx - 1) {
             double KT = kf[j - 1].kTT + kf[j].kTT;
             double KX = kf[j - 1].kTM + kf[j].kTM;
@@ -444,7 +531,7 @@ static double ftcs_bound(const ref_wall *w, const int *lay, const double *T,
     for (int j = 0; j < nx - 1; ++j) kf[j] = face_k(w, lay, T, P, j);
     double best = INFINITY;
     for (int j = 0; j < nx; ++j) {
-        ref_ccoef c = law_c(&w->layer[lay[j]], T[j], P[j]);
+        ref_ccoef c = law_c(w, &w->layer[lay[j]], T[j], P[j]);
         double width = (j == 0 || j == nx - 1) ? 0.5 * dx : dx;
         double gT = 0.0, gM = 0.0;
         if (j > 0) { gT += kf[j - 1].kTT / dx; gM += kf[j - 1].kM / dx; }
@@ -508,7 +595,7 @@ static void ftcs_startup(const ref_sim *s, int64_t w, const int *lay, double *T,
             acc[side][1] += g;
         }
         for (int j = 0; j < nx; ++j) {
-            ref_ccoef c = law_c(&wl->layer[lay[j]], T[j], P[j]);
+            ref_ccoef c = law_c(wl, &wl->layer[lay[j]], T[j], P[j]);
             double width = (j == 0 || j == nx - 1) ? 0.5 * dx : dx;
             double dM = 0.0, dT = 0.0;
             if (j > 0) {
@@ -747,7 +834,7 @@ void ref_get_coeffs(const ref_sim *s, int64_t w, double *node, double *face)
     int64_t o = s->off[w];
     const int *lay = s->lay + o;
     for (int j = 0; j < wl->nx; ++j) {
-        ref_ccoef c = law_c(&wl->layer[lay[j]], s->Tc[o + j], s->Pc[o + j]);
+        ref_ccoef c = law_c(wl, &wl->layer[lay[j]], s->Tc[o + j], s->Pc[o + j]);
         node[3 * j] = c.cTT; node[3 * j + 1] = c.cM; node[3 * j + 2] = c.cTM;
     }
     for (int j = 0; j < wl->nx - 1; ++j) {
@@ -838,7 +925,7 @@ double ref_implicit_run(const ref_wall *w, double dt, double Lv, int64_t nsteps,
                 Ps[j] = theta * Pk[j] + (1.0 - theta) * Po[j];
             }
             for (int j = 0; j < nx - 1; ++j) kf[j] = face_k(w, lay, Ts, Ps, j);
-            for (int j = 0; j < nx; ++j) cn[j] = law_c(&w->layer[lay[j]], Ts[j], Ps[j]);
+            for (int j = 0; j < nx; ++j) cn[j] = law_c(w, &w->layer[lay[j]], Ts[j], Ps[j]);
             /* moisture: width c (P1 - P0)/dt = theta F(P1) + (1-theta) F(P0) */
             for (int j = 0; j < nx; ++j) {
                 double width = (j == 0 || j == nx - 1) ? 0.5 * dx : dx;

@@ -58,10 +58,11 @@ DAY = 86400.0
 DT_OVER_DX_MAX = 1.0 / 3.0e-4
 
 
-def default_config(dt: float = 1.0, startup: int = 0) -> dict:
-    """Global constants of a run (room air defaults rho_a, c_pa, c_pv, Pv_ref)."""
+def default_config(dt: float = 1.0, startup: int = 0, law: int = 0) -> dict:
+    """Global constants of a run (room air defaults rho_a, c_pa, c_pv, Pv_ref);
+    law 0 = the per-layer shape law, 1 = the Table 1 material."""
     return dict(dt=float(dt), Lv=LV, cw=CW, rho_a=1.2, c_pa=1006.0, c_pv=1860.0,
-                Pv_ref=1.61e5, startup=int(startup))
+                Pv_ref=1.61e5, startup=int(startup), law=int(law))
 
 
 def _zero_sine(shape) -> np.ndarray:
@@ -164,6 +165,38 @@ def uniform_batch(n_walls: int, seed: int = 202, nx: int = 1001, L: float = 0.3)
     _sine(w["RHamb"][:, 0], 0.6, AR, DAY / 2, pR)
     _interior_side(w)
     w["T0"][:] = 293.0
+    w["RH0"][:] = 0.5
+    return w
+
+
+def table1_batch(n_walls: int, seed: int = 707, nx: int = 1001, L: float = 0.3,
+                 spread: float = math.sqrt(10.0)) -> dict:
+    """Identical-grid batch under the Table 1 law (run with cfg["law"] = 1):
+    the load-bearing material of Sec. 6 with its four scale multipliers
+    (lambda, k_M and k_TM, rho_0 c_0, c_M and c_TM) log-uniform within a
+    factor ``spread`` of 1, the outdoor air of ``uniform_batch`` on side 0,
+    20 degC / 50 % inside and initially.  30 cm and 1001 nodes keep
+    dt/dx = 3333 s/m at dt = 1 s (the rule of the shape-law batches; with
+    this law the oracle also stays bounded there and diverges at 3e4 s/m)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W = int(n_walls)
+    w = _empty_walls(W)
+    w["nx"][:] = nx
+    w["n_layers"][:] = 1
+    w["layer"][:, 0, LAYER_FIELDS.index("thick")] = L
+    for name in ("k0", "kM0", "c0", "cM0"):
+        w["layer"][:, 0, LAYER_FIELDS.index(name)] = np.exp(
+            rng.uniform(-math.log(spread), math.log(spread), W))
+    AT, pT, AR, pR = _outdoor(rng, W)
+    w["hT"][:, 0] = 25.0
+    w["hM"][:, 0] = 2e-7
+    _sine(w["Tamb"][:, 0], 293.15, AT, DAY, pT)
+    _sine(w["RHamb"][:, 0], 0.6, AR, DAY / 2, pR)
+    w["hT"][:, 1] = 8.0
+    w["hM"][:, 1] = 3e-8
+    _sine(w["Tamb"][:, 1], 293.15, 0.0, DAY, 0.0)
+    _sine(w["RHamb"][:, 1], 0.5, 0.0, DAY / 2, 0.0)
+    w["T0"][:] = 293.15
     w["RH0"][:] = 0.5
     return w
 

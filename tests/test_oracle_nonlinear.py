@@ -67,15 +67,21 @@ def _balance_residuals(sim, w_index, wall, dt, Lv):
     return (m_terms.sum() - m_rhs) / m_scale, (h_terms.sum() - h_rhs) / h_scale
 
 
-@pytest.mark.parametrize("case", ["single", "layered"])
+@pytest.mark.parametrize("case", ["single", "layered", "table1"])
 def test_balance_identity_every_step(case):
-    w = wl.single_wall() if case == "single" else _layered_wall()
+    if case == "table1":               # the Table 1 law, three scaled layers
+        w = _layered_wall()
+        for l in range(3):
+            for k, f in (("k0", 1.3), ("kM0", 0.7), ("c0", 1.1), ("cM0", 0.9)):
+                w["layer"][0, l, wl.LAYER_FIELDS.index(k)] = f ** (l + 1)
+    else:
+        w = wl.single_wall() if case == "single" else _layered_wall()
     dt = 1.0 if case == "single" else 20.0
-    cfg = wl.default_config(dt=dt)
+    cfg = wl.default_config(dt=dt, law=1 if case == "table1" else 0)
     sim = oracle.RefSim(w, cfg)
     sim.step(1)            # start-up step (forward-Euler sub-steps)
     sim.step(500)          # let the surface forcing develop
-    if case == "layered":
+    if case != "single":
         lay = sim.layers(0)
         assert set(lay.tolist()) == {0, 1, 2}
     for _ in range(20):
