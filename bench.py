@@ -37,6 +37,11 @@ DT = 1.0
 # which 2 exponentials and 4 divisions, each counted as one operation (FMA as
 # two).  The per-wall outdoor air and flux work adds < 1 % at 1001 nodes.
 FLOPS_PER_CELL = 69
+# The same count under the Table 1 material law (streaming kernel): face law
+# 73 (face state 4, saturation pressure 5, phi and its log 2, isotherm 36,
+# delta_v 8, k_M 11, scaling 7), node law 51 (saturation pressure 5, phi
+# and its log 2, isotherm 36, capacities 8), updates 31.
+FLOPS_PER_CELL_TABLE1 = 155
 # Minimum HBM bytes per cell-update of a streaming step: read T, P at n-1 and
 # n, write T, P at n+1 (8 B each in FP64, 4 B in FP32).
 BYTES_PER_CELL = {"f64": 48, "f32": 24}
@@ -54,12 +59,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--walls", type=int, default=N_WALLS)
     ap.add_argument("--workload", default="identical",
-                    choices=["identical", "layered", "building", "implicit"],
+                    choices=["identical", "layered", "building", "implicit", "table1"],
                     help="identical: the 65,536 x 1001 batch (the default and the headline); "
                          "layered: 100,000 uneven 1-3 layer walls (FP32, dt = 1 s); "
                          "building: 4,096 rooms x 6 walls coupled to the room-air balance; "
                          "implicit: the identical batch through the Euler-implicit and "
-                         "Crank-Nicolson comparators against DF")
+                         "Crank-Nicolson comparators against DF; table1: the identical "
+                         "grid under the Table 1 material law (streaming schedule)")
     ap.add_argument("--rooms", type=int, default=4096)
     ap.add_argument("--radiation", action="store_true",
                     help="building workload with the radiative surface sources")
@@ -135,7 +141,13 @@ def resident_traffic(dtype):
         return None
 
 
-def roofline(dtype, cells, steps, ms, info):
+def roofline(dtype, cells, steps, ms, info, law=0):
+    if law == 1:                # Table 1 law, streaming: VALU-bound, one launch per step
+        per_launch_s = ms / 1e3 / steps
+        ach = FLOPS_PER_CELL_TABLE1 * cells / per_launch_s / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK[dtype], "unit": "TFLOP/s",
+                "frac": round(ach / PEAK[dtype], 4), "traffic": None, "kernel": "k_df_stream",
+                "launch_ms": round(per_launch_s * 1e3, 4)}
     if info["schedule"] == 2:   # resident: VALU-bound, one launch per chunk
         launches = math.ceil(steps / info["chunk_steps"])
         per_launch_s = ms / 1e3 / launches
@@ -195,7 +207,16 @@ def other_workload(a, torch, dfhm, wl):
     """The uneven layered batch or the building batch: cell-updates/s of the
     resident (or chosen) schedule in FP32 and FP64."""
     rooms = None
-    if a.workload == "layered":
+    law = 0
+    schedule = a.schedule
+    if a.workload == "table1":
+        dt = a.dt or 1.0
+        law = 1
+        schedule = "stream" if a.schedule == "resident" else a.schedule
+        walls = wl.table1_batch(a.walls, seed=707, nx=NX)
+        name = (f"identical-grid batch under the Table 1 material law: {a.walls} walls x {NX} "
+                f"nodes (30 cm), scales within 1.5x of the paper's material, dt = {dt:g} s")
+    elif a.workload == "layered":
         dt = a.dt or 1.0
         walls = wl.layered_batch(100000 if a.walls == N_WALLS else a.walls, seed=303, dt=dt)
         name = (f"uneven batch: {len(walls['nx'])} walls, 1-3 layers, lognormal Nx (median 300, "
@@ -210,7 +231,7 @@ def other_workload(a, torch, dfhm, wl):
                    if a.radiation else "")
                 + (f", rooms linked in chains of {a.link_group} (0.3 h^-1 airflow)"
                    if a.link_group > 1 else ""))
-    cfg = wl.default_config(dt=dt)
+    cfg = wl.default_config(dt=dt, law=law)
     cells = int(wl.total_nodes(walls))
     out = {"metric": "DF cell-updates/s", "unit": "cell-updates/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "higher_is_better": True, "data": "synthetic",
@@ -219,9 +240,9 @@ def other_workload(a, torch, dfhm, wl):
     for key, prec, dtype in (("fp32", dfhm.FP32, "f32"), ("fp64", dfhm.FP64, "f64")):
         if a.precision not in ("both", key):
             continue
-        ms, info, fin = run_gpu(dfhm, walls, cfg, prec, a.schedule, a.steps, a.warmup, rooms)
+        ms, info, fin = run_gpu(dfhm, walls, cfg, prec, schedule, a.steps, a.warmup, rooms)
         out[key] = {"value": cells * a.steps / (ms / 1e3), "ms_per_step": ms / a.steps,
-                    "roofline": roofline(dtype, cells, a.steps, ms, info), "finite": fin,
+                    "roofline": roofline(dtype, cells, a.steps, ms, info, law), "finite": fin,
                     "schedule": ["", "stream", "resident"][info["schedule"]],
                     "block_threads": info["block_threads"],
                     "nodes_per_thread": info["nodes_per_thread"]}

@@ -62,6 +62,10 @@ enum { DFHM_START_FTCS = 0, DFHM_START_REPEAT = 1 };
  * RESIDENT = one persistent launch per chunk of steps, each workgroup keeping
  * its walls' levels on chip; AUTO = chosen by the autotuner. */
 enum { DFHM_SCHED_AUTO = 0, DFHM_SCHED_STREAM = 1, DFHM_SCHED_RESIDENT = 2 };
+/* Material law of a context (dfhm_config.law): SHAPE = the per-layer law
+ * of dfhm_layer below; TABLE1 = the load-bearing material of Sec. 6
+ * (Table 1), see dfhm_layer. */
+enum { DFHM_LAW_SHAPE = 0, DFHM_LAW_TABLE1 = 1 };
 
 /* x(t) = mean + amp * sin(2 pi t / period_s + phase) */
 typedef struct { double mean, amp, period_s, phase; } dfhm_sine;
@@ -75,7 +79,17 @@ typedef struct { double mean, amp, period_s, phase; } dfhm_sine;
  *   c_M  = cM0 (1 + c_M phi)        s2/m2
  *   c_TM = (e_TM + f_TM theta) c_M  (c_TM = c_w T f'/Ps, Sec. 2)
  * All-zero shape coefficients (a_T, a_M, c_T, c_M, f_TM) give the
- * constant-coefficient walls of Sec. 6.1 (Table 2). */
+ * constant-coefficient walls of Sec. 6.1 (Table 2).
+ *
+ * Under DFHM_LAW_TABLE1 (Table 1, with s = -R_v T ln phi the suction in
+ * J/kg, R_v = 461.5, T in K; s = 0 for phi >= 1):
+ *   f    = 47.1 [1 + (1.25e-5 s)^1.65]^-(1-1/1.65) + 109.9 [1 + (1.8e-5 s)^6]^-(5/6)  kg/m3
+ *   k_TT = k0 (0.2 + 0.0045 f)
+ *   k_M  = kM0 (1.97e-10 10^(1.44 - 0.07 log10(2 phi)) + 1.77e-7 exp(-8 (2 phi - 2)^2))
+ *   k_TM = kM0 Lv delta_v,  delta_v = 1.88e-6/T (1 - f/157) / (0.503 (1 - f/157)^2 + 0.497)
+ *   c_TT = c0 790 x 870 + cw f,  c_M = cM0 (df/dphi) / Ps,  c_TM = cw theta c_M
+ * so that k0 = kM0 = c0 = cM0 = 1 is the paper's material; the other fields
+ * are ignored.  This law runs on the streaming schedule only. */
 typedef struct {
     double thickness_m;
     double k0, a_T, kM0, a_M, b_TM, c0, c_T, cM0, c_M, e_TM, f_TM;
@@ -142,7 +156,8 @@ typedef struct {
     int32_t block_threads;  /* resident: threads per workgroup; 0 = autotune */
     int32_t nodes_per_thread; /* resident: nodes per thread; 0 = autotune */
     int32_t use_graph;      /* stream schedule: replay captured chunks (1) */
-    int32_t reserved;
+    int32_t law;            /* DFHM_LAW_* (DFHM_LAW_TABLE1 excludes
+                               DFHM_SCHED_RESIDENT: DFHM_E_INVAL) */
 } dfhm_config;
 
 /* Device bytes the wall state of a batch needs (levels, node layer ids,

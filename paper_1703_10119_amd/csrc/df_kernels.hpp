@@ -174,7 +174,8 @@ __device__ __forceinline__ void surface_flux(const WallDev &W, int side, double 
 
 // EXT: radiative sources present in the batch (incident flux or long-wave
 // exchange); without them the surface lanes skip that code entirely.
-template <typename R, bool EXT>
+// LAW: 0 = shape law, 1 = the Table 1 law.
+template <typename R, bool EXT, int LAW>
 __global__ void __launch_bounds__(kStreamBlock)
 k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
             R *T0b, R *T1b, R *P0b, R *P1b, const uint8_t *__restrict__ lay,
@@ -219,7 +220,10 @@ k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
         Pr = Pc[j + 1];
         R thf = thr + (R)0.5 * (Tj + Tr);
         R Pf = pr + (R)0.5 * (Pj + Pr);
-        if (!layered) kr = face_k<R>(W, 0, 0, thf, Pf);
+        if constexpr (LAW == 1) {
+            const int la = layered ? ly[j] : 0, lb = layered ? ly[j + 1] : 0;
+            kr = t1_face_k<R>(W, la, lb, thf, Pf, (R)rc.Lv);
+        } else if (!layered) kr = face_k<R>(W, 0, 0, thf, Pf);
         else {
             int la = ly[j], lb = ly[j + 1];
             R phi = Pf / psat_th(thf);
@@ -243,8 +247,9 @@ k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
     const double *m = layered ? s_lay[ly[j]] : W.lay[0];
     const R th = thr + Tj;
     const R P = pr + Pj;
-    const R phi = P / psat_th(th);
-    const CCoef<R> c = law_c<R>(m, phi, th);
+    CCoef<R> c;
+    if constexpr (LAW == 1) c = t1_law_c<R>(m, th, P, (R)rc.cw);
+    else c = law_c<R>(m, P / psat_th(th), th);
     const R r = (R)W.r;
     const R Tm = Tp[j], Pm = Pp[j];
     R Tn, Pn;
@@ -302,7 +307,7 @@ k_startup(const WallDev *__restrict__ walls, R *T0b, R *T1b, R *P0b, R *P1b,
           const uint8_t *__restrict__ lay, const double *__restrict__ roomT,
           const double *__restrict__ roomP, const RoomDev *__restrict__ rooms,
           const int32_t *__restrict__ room_walls, double *__restrict__ flux,
-          int *__restrict__ bad, RunConst rc)
+          int *__restrict__ bad, RunConst rc, int law)
 {
     __shared__ double sT[kMaxNx], sP[kMaxNx], skT[kMaxNx], skM[kMaxNx], skX[kMaxNx];
     __shared__ uint8_t sl[kMaxNx];
@@ -322,11 +327,16 @@ k_startup(const WallDev *__restrict__ walls, R *T0b, R *T1b, R *P0b, R *P1b,
     }
     __syncthreads();
 
+    auto node_c = [&](const double *m, double T, double P) {
+        return law == 1 ? t1_law_c<double>(m, T - 273.15, P, rc.cw)
+                        : law_c<double>(m, P / psat_th(T - 273.15), T - 273.15);
+    };
     auto faces = [&]() {
         for (int j = tid; j < nx - 1; j += kStartBlock) {
             double Tf = 0.5 * (sT[j] + sT[j + 1]);
             double Pf = 0.5 * (sP[j] + sP[j + 1]);
-            KCoef<double> k = face_k<double>(W, sl[j], sl[j + 1], Tf - 273.15, Pf);
+            KCoef<double> k = law == 1 ? t1_face_k<double>(W, sl[j], sl[j + 1], Tf - 273.15, Pf, rc.Lv)
+                                       : face_k<double>(W, sl[j], sl[j + 1], Tf - 273.15, Pf);
             skT[j] = k.kT;
             skM[j] = k.kM;
             skX[j] = k.kX;
@@ -338,8 +348,7 @@ k_startup(const WallDev *__restrict__ walls, R *T0b, R *T1b, R *P0b, R *P1b,
     __syncthreads();
     double best = INFINITY;
     for (int j = tid; j < nx; j += kStartBlock) {
-        double phi = sP[j] / psat_th(sT[j] - 273.15);
-        CCoef<double> c = law_c<double>(W.lay[sl[j]], phi, sT[j] - 273.15);
+        CCoef<double> c = node_c(W.lay[sl[j]], sT[j], sP[j]);
         double width = (j == 0 || j == nx - 1) ? 0.5 * dx : dx;
         double gT = 0.0, gM = 0.0;
         if (j > 0) { gT += skT[j - 1] / dx; gM += skM[j - 1] / dx; }
@@ -400,8 +409,7 @@ k_startup(const WallDev *__restrict__ walls, R *T0b, R *T1b, R *P0b, R *P1b,
         int q = 0;
         for (int j = tid; j < nx; j += kStartBlock, ++q) {
             double T = sT[j], P = sP[j];
-            double phi = P / psat_th(T - 273.15);
-            CCoef<double> c = law_c<double>(W.lay[sl[j]], phi, T - 273.15);
+            CCoef<double> c = node_c(W.lay[sl[j]], T, P);
             double width = (j == 0 || j == nx - 1) ? 0.5 * dx : dx;
             double dM = 0.0, dT = 0.0;
             if (j > 0) {

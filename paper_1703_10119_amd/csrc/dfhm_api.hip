@@ -249,7 +249,9 @@ dfhm_status check_bad(dfhm_ctx *c)
 template <typename R>
 dfhm_status launch_stream_step(dfhm_ctx *c, int off)
 {
-    auto kern = c->extended ? k_df_stream<R, true> : k_df_stream<R, false>;
+    auto kern = c->cfg.law == DFHM_LAW_TABLE1
+                    ? (c->extended ? k_df_stream<R, true, 1> : k_df_stream<R, false, 1>)
+                    : (c->extended ? k_df_stream<R, true, 0> : k_df_stream<R, false, 0>);
     hipLaunchKernelGGL(kern, dim3(c->ntiles), dim3(kStreamBlock), 0, c->stream,
                        c->d_walls, c->d_tiles, (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0],
                        (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_rooms,
@@ -279,7 +281,7 @@ dfhm_status launch_startup(dfhm_ctx *c)
     hipLaunchKernelGGL(k_startup<R>, dim3((unsigned)c->nw), dim3(kStartBlock), 0, c->stream,
                        c->d_walls, (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0],
                        (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_rooms,
-                       c->d_room_walls, c->d_flux, c->d_bad, c->rc);
+                       c->d_room_walls, c->d_flux, c->d_bad, c->rc, c->cfg.law);
     return DFHM_OK;
 }
 
@@ -528,7 +530,9 @@ Cand default_shape(const dfhm_ctx *c)
 dfhm_status ensure_packing(dfhm_ctx *c)
 {
     if (!c->shape_uniform)
-        return fail(c, DFHM_E_INVAL, "the resident schedule needs one law shape for all walls");
+        return fail(c, DFHM_E_INVAL, c->cfg.law != DFHM_LAW_SHAPE
+                                         ? "the Table 1 law runs on the streaming schedule"
+                                         : "the resident schedule needs one law shape for all walls");
     int nt = c->res_threads, npt = c->res_npt;
     if (c->cfg.block_threads > 0 && c->cfg.nodes_per_thread > 0) {
         nt = c->cfg.block_threads;
@@ -683,6 +687,7 @@ dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t 
     if (cfg->startup != DFHM_START_FTCS && cfg->startup != DFHM_START_REPEAT) return DFHM_E_INVAL;
     if (cfg->schedule < DFHM_SCHED_AUTO || cfg->schedule > DFHM_SCHED_RESIDENT) return DFHM_E_INVAL;
     if (cfg->chunk_steps < 0 || cfg->block_threads < 0 || cfg->nodes_per_thread < 0) return DFHM_E_INVAL;
+    if (cfg->law != DFHM_LAW_SHAPE && cfg->law != DFHM_LAW_TABLE1) return DFHM_E_INVAL;
     int64_t N = 0;
     for (int64_t i = 0; i < n_walls; ++i) {
         if (!check_wall(walls[i], i).empty()) return DFHM_E_INVAL;
@@ -741,7 +746,8 @@ dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t 
     c->ntiles = (int)tiles.size();
     c->wall_room.assign(n_walls, -1);
     c->room_side.assign(n_walls, 1);
-    c->shape_uniform = shape_of(walls, n_walls, c->shape);
+    // the resident kernel implements the shape law only
+    c->shape_uniform = cfg->law == DFHM_LAW_SHAPE && shape_of(walls, n_walls, c->shape);
     if (cfg->schedule == DFHM_SCHED_RESIDENT && !c->shape_uniform) {
         delete c;
         return DFHM_E_INVAL;
@@ -1330,6 +1336,7 @@ uint64_t describe(const dfhm_ctx *c)
     }
     mix(c->wall_room.data(), sizeof(int64_t) * c->wall_room.size());
     mix(&c->nr, sizeof c->nr);
+    if (c->cfg.law != DFHM_LAW_SHAPE) mix(&c->cfg.law, sizeof c->cfg.law);
     for (const auto &p : c->zone_partners)       // linked zones (none: nothing mixed)
         if (!p.empty()) mix(p.data(), sizeof(int32_t) * p.size());
     return h;

@@ -198,6 +198,103 @@ __device__ __forceinline__ double exp_bounded(double a)
 }
 __device__ __forceinline__ float exp_bounded(float a) { return __expf(a); }
 
+// ------------------------------------------------- Table 1 material law
+// The load-bearing material of Sec. 6 (Table 1), read as follows (every
+// coefficient of Table 2 is reproduced within 1.5 % at 20 degC):
+//   suction s = -R_v T ln(phi) (J/kg, Kelvin's law with rho_l dropped);
+//   f = sum_i w_i [1 + (c_i s)^n_i]^(-m_i), (w, c, n) = (47.1, 1.25e-5, 1.65)
+//       and (109.9, 1.8e-5, 6), m_i = 1 - 1/n_i;
+//   c_M = (df/dphi) / P_s, c_TT = rho_0 c_0 + c_w f, c_TM = c_w theta c_M;
+//   k_TT = 0.2 + 0.0045 f, k_TM = L_v delta_v,
+//   delta_v = 1.88e-6 / T (1 - f/157) / (0.503 (1 - f/157)^2 + 0.497),
+//   k_M = 1.97e-10 10^(1.44 - 0.07 log10(2 phi)) + 1.77e-7 exp(-8 (2 phi - 2)^2).
+// A layer's k0, kM0, c0 and cM0 multiply lambda, (k_M, k_TM), rho_0 c_0 and
+// (c_M, c_TM).  Powers are written as exponentials of logarithms (FP64: the
+// bounded exponential above and the library logarithm; FP32: the hardware
+// base-2 exponential and logarithm).
+constexpr double kT1Rv = 461.5, kT1Rho0c0 = 790.0 * 870.0;
+
+__device__ __forceinline__ double t1_ln(double x) { return log(x); }
+__device__ __forceinline__ float t1_ln(float x) { return __builtin_amdgcn_logf(x) * 0.69314718f; }
+__device__ __forceinline__ double t1_exp(double x) { return exp_bounded(x); }
+__device__ __forceinline__ float t1_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504f); }
+
+// Moisture content f and df/dphi at temperature T (K), given ln(phi).
+template <typename R>
+__device__ __forceinline__ void t1_isotherm(R T, R lnphi, R &f, R &dfdphi_phi)
+{
+    // s is clamped away from 0 (phi >= 1): the powers then vanish
+    const R s = fmax(-(R)kT1Rv * T * lnphi, (R)1e-30);
+    // mode 1: n = 1.65, m = 1 - 1/1.65
+    const R m1 = (R)(1.0 - 1.0 / 1.65);
+    const R l1 = t1_ln((R)1.25e-5 * s);
+    const R a1 = (R)1 + t1_exp((R)1.65 * l1);
+    const R la1 = t1_ln(a1);
+    const R f1 = (R)47.1 * t1_exp(-m1 * la1);
+    const R g1 = (R)(47.1 * (1.0 - 1.0 / 1.65) * 1.65 * 1.25e-5) * t1_exp((R)0.65 * l1 - (m1 + (R)1) * la1);
+    // mode 2: n = 6, m = 5/6 (integer powers by products)
+    const R m2 = (R)(5.0 / 6.0);
+    const R x = (R)1.8e-5 * s;
+    const R x2 = x * x, x4 = x2 * x2;
+    const R la2 = t1_ln((R)1 + x4 * x2);
+    const R f2 = (R)109.9 * t1_exp(-m2 * la2);
+    const R g2 = (R)(109.9 * (5.0 / 6.0) * 6.0 * 1.8e-5) * (x4 * x) * t1_exp(-(m2 + (R)1) * la2);
+    f = f1 + f2;
+    // -df/ds = g1 + g2; ds/dphi = -R_v T / phi: phi df/dphi = (g1 + g2) R_v T
+    dfdphi_phi = (g1 + g2) * ((R)kT1Rv * T);
+}
+
+// Conductivities of the Table 1 law at (theta, P) for layer scales m.
+template <typename R>
+__device__ __forceinline__ KCoef<R> t1_law_k(const double *m, R th, R P, R Lv)
+{
+    const R T = th + (R)273.15;
+    const R phi = P / psat_th(th);
+    const R lnphi = t1_ln(phi);
+    R f, g;
+    t1_isotherm<R>(T, lnphi, f, g);
+    const R u = (R)1 - f * (R)(1.0 / 157.0);
+    const R dv = div_nr((R)1.88e-6 * u, T * ((R)0.503 * u * u + (R)0.497));
+    // 10^(1.44 - 0.07 log10(2 phi)) = 10^1.44 (2 phi)^(-0.07)
+    const R a = (R)2 * phi - (R)2;
+    const R kM = (R)(1.97e-10 * 27.542287033381662) * t1_exp((R)-0.07 * (lnphi + (R)0.69314718055994531)) +
+                 (R)1.77e-7 * t1_exp((R)-8 * a * a);
+    KCoef<R> k;
+    k.kT = (R)m[L_K0] * ((R)0.2 + (R)0.0045 * f);
+    k.kM = (R)m[L_KM0] * kM;
+    k.kX = (R)m[L_KM0] * Lv * dv;
+    return k;
+}
+
+// Capacities of the Table 1 law at (theta, P) for layer scales m.
+template <typename R>
+__device__ __forceinline__ CCoef<R> t1_law_c(const double *m, R th, R P, R cw)
+{
+    const R T = th + (R)273.15;
+    const R ps = psat_th(th);
+    R f, g;
+    t1_isotherm<R>(T, t1_ln(P / ps), f, g);
+    CCoef<R> c;
+    c.cT = (R)m[L_C0] * (R)kT1Rho0c0 + cw * f;
+    c.cM = (R)m[L_CM0] * div_nr(g, P);          // (df/dphi) / P_s = (phi df/dphi) / P
+    c.cX = cw * th * c.cM;
+    return c;
+}
+
+// Face conductivities under the Table 1 law (harmonic mean across layers).
+template <typename R>
+__device__ __forceinline__ KCoef<R> t1_face_k(const WallDev &W, int la, int lb, R thf, R Pf, R Lv)
+{
+    KCoef<R> a = t1_law_k<R>(W.lay[la], thf, Pf, Lv);
+    if (la == lb) return a;
+    KCoef<R> b = t1_law_k<R>(W.lay[lb], thf, Pf, Lv);
+    KCoef<R> k;
+    k.kT = harm(a.kT, b.kT);
+    k.kM = harm(a.kM, b.kM);
+    k.kX = harm(a.kX, b.kX);
+    return k;
+}
+
 // Neumaier (1974) compensated accumulation.
 __device__ __forceinline__ void neumaier_add(double &s, double &c, double x)
 {

@@ -64,7 +64,7 @@ class Config(C.Structure):
                 ("cw", C.c_double), ("rho_a", C.c_double), ("c_pa", C.c_double),
                 ("c_pv", C.c_double), ("Pv_ref", C.c_double), ("stream", C.c_void_p),
                 ("block_threads", C.c_int32), ("nodes_per_thread", C.c_int32),
-                ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("use_graph", C.c_int32), ("law", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -313,6 +313,7 @@ class Solver:
         c.block_threads = int(threads)
         c.nodes_per_thread = int(npt)
         c.use_graph = int(use_graph)
+        c.law = int(cfg.get("law", 0))
         self._cfg = c
         self._walls = walls_struct_fast(walls) if self.W > 256 else walls_struct(walls)
         self._arena = None

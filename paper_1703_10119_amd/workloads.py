@@ -170,14 +170,18 @@ def uniform_batch(n_walls: int, seed: int = 202, nx: int = 1001, L: float = 0.3)
 
 
 def table1_batch(n_walls: int, seed: int = 707, nx: int = 1001, L: float = 0.3,
-                 spread: float = math.sqrt(10.0)) -> dict:
+                 spread: float = 1.5) -> dict:
     """Identical-grid batch under the Table 1 law (run with cfg["law"] = 1):
     the load-bearing material of Sec. 6 with its four scale multipliers
     (lambda, k_M and k_TM, rho_0 c_0, c_M and c_TM) log-uniform within a
     factor ``spread`` of 1, the outdoor air of ``uniform_batch`` on side 0,
-    20 degC / 50 % inside and initially.  30 cm and 1001 nodes keep
-    dt/dx = 3333 s/m at dt = 1 s (the rule of the shape-law batches; with
-    this law the oracle also stays bounded there and diverges at 3e4 s/m)."""
+    20 degC / 50 % inside and initially.  30 cm and 1001 nodes give
+    dt/dx = 3333 s/m at dt = 1 s.  Under this law (its k_TM = L_v delta_v is
+    about 20x the shape law's) the nonlinear DF step is more fragile: with
+    spread 2 at dt = 1 s, 4 of 65,536 walls (heat diffusivity about 3x the
+    material's) diverge within 50 steps, in the oracle and on the GPU alike;
+    with spread 1.5 all 65,536 stay bounded for 6000 steps, as they do with
+    spread 2 at dt = 0.5 s."""
     rng = np.random.Generator(np.random.PCG64(seed))
     W = int(n_walls)
     w = _empty_walls(W)
