@@ -214,7 +214,32 @@ __device__ __forceinline__ float exp_bounded(float a) { return __expf(a); }
 // base-2 exponential and logarithm).
 constexpr double kT1Rv = 461.5, kT1Rho0c0 = 790.0 * 870.0;
 
-__device__ __forceinline__ double t1_ln(double x) { return log(x); }
+// ln(x) for a positive normal x: x = m 2^e with m in [1/sqrt2, sqrt2), then
+// ln m = 2 artanh(z), z = (m - 1)/(m + 1), |z| <= 0.1716, by its Taylor
+// series through z^21 (truncation below 1e-18 relative), and e ln2 with ln2
+// split into a head and a tail.
+__device__ __forceinline__ double log_bounded(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.70710678118654752440) { m *= 2.0; e -= 1; }
+    const double z = div_nr(m - 1.0, m + 1.0);
+    const double z2 = z * z;
+    double p = 1.0 / 21.0;
+    p = fma(p, z2, 1.0 / 19.0);
+    p = fma(p, z2, 1.0 / 17.0);
+    p = fma(p, z2, 1.0 / 15.0);
+    p = fma(p, z2, 1.0 / 13.0);
+    p = fma(p, z2, 1.0 / 11.0);
+    p = fma(p, z2, 1.0 / 9.0);
+    p = fma(p, z2, 1.0 / 7.0);
+    p = fma(p, z2, 1.0 / 5.0);
+    p = fma(p, z2, 1.0 / 3.0);
+    p = fma(p, z2, 1.0);
+    const double de = (double)e;
+    return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * z * p));
+}
+__device__ __forceinline__ double t1_ln(double x) { return log_bounded(x); }
 __device__ __forceinline__ float t1_ln(float x) { return __builtin_amdgcn_logf(x) * 0.69314718f; }
 __device__ __forceinline__ double t1_exp(double x) { return exp_bounded(x); }
 __device__ __forceinline__ float t1_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504f); }
@@ -225,31 +250,42 @@ __device__ __forceinline__ void t1_isotherm(R T, R lnphi, R &f, R &dfdphi_phi)
 {
     // s is clamped away from 0 (phi >= 1): the powers then vanish
     const R s = fmax(-(R)kT1Rv * T * lnphi, (R)1e-30);
-    // mode 1: n = 1.65, m = 1 - 1/1.65
+    // mode 1: n = 1.65, m = 1 - 1/1.65; with p = x^n, a = 1 + p and e = a^-m
+    // the derivative term x^(n-1) a^(-m-1) is p e / (x a): four
+    // transcendentals and one division instead of five transcendentals
     const R m1 = (R)(1.0 - 1.0 / 1.65);
-    const R l1 = t1_ln((R)1.25e-5 * s);
-    const R a1 = (R)1 + t1_exp((R)1.65 * l1);
-    const R la1 = t1_ln(a1);
-    const R f1 = (R)47.1 * t1_exp(-m1 * la1);
-    const R g1 = (R)(47.1 * (1.0 - 1.0 / 1.65) * 1.65 * 1.25e-5) * t1_exp((R)0.65 * l1 - (m1 + (R)1) * la1);
-    // mode 2: n = 6, m = 5/6 (integer powers by products)
+    const R x1 = (R)1.25e-5 * s;
+    const R p1 = t1_exp((R)1.65 * t1_ln(x1));
+    const R a1 = (R)1 + p1;
+    const R e1 = t1_exp(-m1 * t1_ln(a1));
+    const R f1 = (R)47.1 * e1;
+    const R g1 = (R)(47.1 * (1.0 - 1.0 / 1.65) * 1.65 * 1.25e-5) * div_nr(p1 * e1, x1 * a1);
+    // mode 2: n = 6, m = 5/6 (integer powers by products; a^(-m-1) = e / a)
     const R m2 = (R)(5.0 / 6.0);
     const R x = (R)1.8e-5 * s;
     const R x2 = x * x, x4 = x2 * x2;
-    const R la2 = t1_ln((R)1 + x4 * x2);
-    const R f2 = (R)109.9 * t1_exp(-m2 * la2);
-    const R g2 = (R)(109.9 * (5.0 / 6.0) * 6.0 * 1.8e-5) * (x4 * x) * t1_exp(-(m2 + (R)1) * la2);
+    const R a2 = (R)1 + x4 * x2;
+    const R e2 = t1_exp(-m2 * t1_ln(a2));
+    const R f2 = (R)109.9 * e2;
+    const R g2 = (R)(109.9 * (5.0 / 6.0) * 6.0 * 1.8e-5) * div_nr((x4 * x) * e2, a2);
     f = f1 + f2;
     // -df/ds = g1 + g2; ds/dphi = -R_v T / phi: phi df/dphi = (g1 + g2) R_v T
     dfdphi_phi = (g1 + g2) * ((R)kT1Rv * T);
 }
+
+// Magnus saturation pressure for the Table 1 law (bounded exponential).
+__device__ __forceinline__ double t1_psat(double th)
+{
+    return 610.94 * exp_bounded(div_nr(17.625 * th, th + 243.04));
+}
+__device__ __forceinline__ float t1_psat(float th) { return psat_th(th); }
 
 // Conductivities of the Table 1 law at (theta, P) for layer scales m.
 template <typename R>
 __device__ __forceinline__ KCoef<R> t1_law_k(const double *m, R th, R P, R Lv)
 {
     const R T = th + (R)273.15;
-    const R phi = P / psat_th(th);
+    const R phi = div_nr(P, t1_psat(th));
     const R lnphi = t1_ln(phi);
     R f, g;
     t1_isotherm<R>(T, lnphi, f, g);
@@ -271,9 +307,9 @@ template <typename R>
 __device__ __forceinline__ CCoef<R> t1_law_c(const double *m, R th, R P, R cw)
 {
     const R T = th + (R)273.15;
-    const R ps = psat_th(th);
+    const R ps = t1_psat(th);
     R f, g;
-    t1_isotherm<R>(T, t1_ln(P / ps), f, g);
+    t1_isotherm<R>(T, t1_ln(div_nr(P, ps)), f, g);
     CCoef<R> c;
     c.cT = (R)m[L_C0] * (R)kT1Rho0c0 + cw * f;
     c.cM = (R)m[L_CM0] * div_nr(g, P);          // (df/dphi) / P_s = (phi df/dphi) / P
