@@ -89,7 +89,7 @@ typedef struct { double mean, amp, period_s, phase; } dfhm_sine;
  *   k_TM = kM0 Lv delta_v,  delta_v = 1.88e-6/T (1 - f/157) / (0.503 (1 - f/157)^2 + 0.497)
  *   c_TT = c0 790 x 870 + cw f,  c_M = cM0 (df/dphi) / Ps,  c_TM = cw theta c_M
  * so that k0 = kM0 = c0 = cM0 = 1 is the paper's material; the other fields
- * are ignored.  This law runs on the streaming schedule only. */
+ * are ignored. */
 typedef struct {
     double thickness_m;
     double k0, a_T, kM0, a_M, b_TM, c0, c_T, cM0, c_M, e_TM, f_TM;
@@ -156,8 +156,7 @@ typedef struct {
     int32_t block_threads;  /* resident: threads per workgroup; 0 = autotune */
     int32_t nodes_per_thread; /* resident: nodes per thread; 0 = autotune */
     int32_t use_graph;      /* stream schedule: replay captured chunks (1) */
-    int32_t law;            /* DFHM_LAW_* (DFHM_LAW_TABLE1 excludes
-                               DFHM_SCHED_RESIDENT: DFHM_E_INVAL) */
+    int32_t law;            /* DFHM_LAW_* */
 } dfhm_config;
 
 /* Device bytes the wall state of a batch needs (levels, node layer ids,

@@ -102,18 +102,19 @@ struct ResIO {
 // Dynamic LDS layout of one workgroup for nt lanes, mw walls and mr zones:
 // halos and faces need one buffer each (a step's reads of them end before the
 // barrier that precedes their next write).
-template <typename R> __host__ __device__ constexpr size_t res_off_rc(int nt)
+// (The Table 1 law keeps a third lane-boundary face value, k_TM.)
+template <typename R> __host__ __device__ constexpr size_t res_off_rc(int nt, int law)
 {
-    return ((sizeof(R) * 6 * (size_t)nt) + 15) & ~(size_t)15;
+    return ((sizeof(R) * (law ? 7 : 6) * (size_t)nt) + 15) & ~(size_t)15;
 }
-template <typename R> __host__ __device__ constexpr size_t res_off_walls(int nt)
+template <typename R> __host__ __device__ constexpr size_t res_off_walls(int nt, int law)
 {
-    return res_off_rc<R>(nt) + 64;
+    return res_off_rc<R>(nt, law) + 64;
 }
 template <typename R> __host__ __device__ constexpr size_t res_lds_bytes(int nt, int mw, int mr,
-                                                                        bool ext)
+                                                                        bool ext, int law)
 {
-    return res_off_walls<R>(nt) + (sizeof(WallRec<R>) + (ext ? sizeof(RadRec) : 0)) * (size_t)mw +
+    return res_off_walls<R>(nt, law) + (sizeof(WallRec<R>) + (ext ? sizeof(RadRec) : 0)) * (size_t)mw +
            sizeof(RoomRec) * (size_t)mr;
 }
 
@@ -159,7 +160,11 @@ template <typename R, int NPT, int NT> constexpr int res_waves_per_eu()
 constexpr int kModePlain = 0;   // walls without zones or radiative sources
 constexpr int kModeZones = 1;   // zones coupled to walls
 constexpr int kModeExt = 2;     // radiative sources and / or linked zones
-template <typename R, int NPT, int NT, int MODE>
+// LAW: 0 = the shape law (scales x the launch's common shape factors),
+// 1 = the Table 1 law (scales x that material's functions, which factor the
+// same way: k_TT = k0 lambda, k_M = kM0 K, k_TM = kM0 L_v delta_v, so the
+// harmonic interface means of the scale tables still apply).
+template <typename R, int NPT, int NT, int MODE, int LAW>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT>())))
 k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ block_walls,
               const int32_t *__restrict__ block_rooms, const WallDev *__restrict__ walls,
@@ -177,9 +182,9 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                   "records keep 16-byte alignment");
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int nthreads = NT;
-    constexpr size_t kRc = res_off_rc<R>(NT), kWalls = res_off_walls<R>(NT);
+    constexpr size_t kRc = res_off_rc<R>(NT, LAW), kWalls = res_off_walls<R>(NT, LAW);
     R *halo = (R *)lds;                                  // [4][NT]
-    R *facb = halo + 4 * NT;                             // [2][NT]
+    R *facb = halo + 4 * NT;                             // [2][NT], [3][NT] under the Table 1 law
     double *s_rc = (double *)(lds + kRc);                // dt, Lv, rho_a, c_pa, c_pv, Pv_ref
     WallRec<R> *wr = (WallRec<R> *)(lds + kWalls);
     RadRec *xr = (RadRec *)(lds + kWalls + sizeof(WallRec<R>) * (size_t)mw);   // EXT only
@@ -260,6 +265,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         for (int e = 0; e < 8; ++e) { X.fk[e][2] = Store<R>::thref(W); X.fk[e][3] = Store<R>::pref(W); }
         X.fk[kFaceNone][0] = X.fk[kFaceNone][1] = (R)0;
         X.fk[7][0] = X.fk[7][1] = (R)0;
+        if constexpr (LAW == 1) X.fk[7][0] = (R)(rc.cw * rinv);   // c_w / r of the moisture heat
     }
     // each zone's wall slots, and its inter-zone links: partner zones sit in
     // this workgroup (the packer keeps linked zones together); resolve them to
@@ -455,10 +461,27 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                     xr[s].qx[par][side] += xr[s].esig * (S4 - (double)m * pow4(wr[s].surf[par][side][0]));
                 }
         }
-        R kT[NPT], kM[NPT], phn[NPT];
+        R kT[NPT], kM[NPT], phn[NPT], kX[NPT];
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
             const Quad<R> k0 = lds_scales<R>(lds, koff[q]);
+            if constexpr (LAW == 1) {
+                // Table 1 law at the face state; a node without a right face
+                // gets zeros (its own state may be padding at 0 K)
+                const bool live = (info[q] >> 13) != kFaceNone;
+                const R Tr = q + 1 < NPT ? Tn[q + 1 < NPT ? q + 1 : q] : Tr_nb;
+                const R Pr = q + 1 < NPT ? Pn[q + 1 < NPT ? q + 1 : q] : Pr_nb;
+                const R thf = live ? fma((R)0.5, Tn[q] + Tr, k0.th) : (R)20;
+                const R Pf = live ? fma((R)0.5, Pn[q] + Pr, k0.p) : (R)1000;
+                const KCoef<R> g = t1_kfun<R>(thf, Pf, (R)s_rc[1]);
+                kT[q] = live ? k0.a * g.kT : (R)0;
+                kM[q] = live ? k0.b * g.kM : (R)0;
+                kX[q] = live ? k0.b * g.kX : (R)0;
+                phn[q] = 0;
+                SCHED_FENCE();
+                continue;
+            }
+            kX[q] = 0;
             const R thr = k0.th, pr = k0.p;
             // a node without a right face (wall end, padding) has zero scales;
             // its face state is its own, so that nothing from the next wall or
@@ -490,24 +513,41 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         }
         facb[t] = kT[NPT - 1];
         facb[nthreads + t] = kM[NPT - 1];
+        if constexpr (LAW == 1) facb[2 * nthreads + t] = kX[NPT - 1];
         __syncthreads();
         // ---- C: node updates (moisture, then heat with the new Pv)
         const R klT = t > 0 ? facb[t - 1] : (R)0;
         const R klM = t > 0 ? facb[nthreads + t - 1] : (R)0;
+        R klX = 0;
+        if constexpr (LAW == 1) klX = t > 0 ? facb[2 * nthreads + t - 1] : (R)0;
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
             const int f = info[q];
             const Quad<R> c0 = lds_scales<R>(lds, coff[q]);
             const R pr = c0.p;
             const R th = c0.th + Tn[q];
-            const R phi = phn[q];
-            const R ccT = c0.a * fma(cT, phi, (R)1);
-            const R ccM = c0.b * fma(aC, phi, (R)1);
-            const R ccX = fma(fTM, th, eTM) * ccM;
+            R ccT, ccM, ccX, lX, kXq;
             const R lT = q > 0 ? kT[q > 0 ? q - 1 : 0] : klT;
             const R lM = q > 0 ? kM[q > 0 ? q - 1 : 0] : klM;
-            const R lX = bTM * lM;
-            const R kXq = bTM * kM[q];
+            if constexpr (LAW == 1) {
+                // capacities of the Table 1 law (divided by r like the scales):
+                // c_TT = c0 rho_0 c_0 + c_w f, c_M = cM0 (df/dphi)/P_s, c_TM = c_w theta c_M
+                const R P = pr + Pn[q];
+                R fw, gw;
+                t1_isotherm<R>(th + (R)273.15, t1_ln(div_nr(P, t1_psat(th))), fw, gw);
+                ccT = fma(c0.a, (R)kT1Rho0c0, wr[f & 0xff].fk[7][0] * fw);
+                ccM = c0.b * div_nr(gw, P);
+                ccX = ((R)rc.cw * th) * ccM;
+                lX = q > 0 ? kX[q > 0 ? q - 1 : 0] : klX;
+                kXq = kX[q];
+            } else {
+                const R phi = phn[q];
+                ccT = c0.a * fma(cT, phi, (R)1);
+                ccM = c0.b * fma(aC, phi, (R)1);
+                ccX = fma(fTM, th, eTM) * ccM;
+                lX = bTM * lM;
+                kXq = bTM * kM[q];
+            }
             const R Tl = q > 0 ? Tn[q > 0 ? q - 1 : 0] : Tl_nb;
             const R Pl = q > 0 ? Pn[q > 0 ? q - 1 : 0] : Pl_nb;
             const R Tr = q + 1 < NPT ? Tn[q + 1 < NPT ? q + 1 : q] : Tr_nb;

@@ -530,9 +530,7 @@ Cand default_shape(const dfhm_ctx *c)
 dfhm_status ensure_packing(dfhm_ctx *c)
 {
     if (!c->shape_uniform)
-        return fail(c, DFHM_E_INVAL, c->cfg.law != DFHM_LAW_SHAPE
-                                         ? "the Table 1 law runs on the streaming schedule"
-                                         : "the resident schedule needs one law shape for all walls");
+        return fail(c, DFHM_E_INVAL, "the resident schedule needs one law shape for all walls");
     int nt = c->res_threads, npt = c->res_npt;
     if (c->cfg.block_threads > 0 && c->cfg.nodes_per_thread > 0) {
         nt = c->cfg.block_threads;
@@ -567,23 +565,23 @@ void refresh_io(dfhm_ctx *c)
     c->io_valid = true;
 }
 
-template <typename R, int NPT, int NT, int MODE>
+template <typename R, int NPT, int NT, int MODE, int LAW>
 void launch_res(dfhm_ctx *c, int k)
 {
     refresh_io(c);
     static bool attr_set = false;   // the largest tables need more than 64 KB of LDS
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT, MODE>,
+        (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT, MODE, LAW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)res_lds_bytes<R>(NT, kResMaxWalls, kResMaxRooms,
-                                                        MODE == kModeExt));
+                                                        MODE == kModeExt, LAW));
         attr_set = true;
     }
     // LDS records sized by the largest wall / zone count of a workgroup of
     // this packing (at least one of each)
     const int mw = std::max(1, c->max_wpb), mr = std::max(1, c->max_rpb);
-    hipLaunchKernelGGL((k_df_resident<R, NPT, NT, MODE>), dim3(c->n_blocks), dim3(NT),
-                       res_lds_bytes<R>(NT, mw, mr, MODE == kModeExt), c->stream, c->d_blocks,
+    hipLaunchKernelGGL((k_df_resident<R, NPT, NT, MODE, LAW>), dim3(c->n_blocks), dim3(NT),
+                       res_lds_bytes<R>(NT, mw, mr, MODE == kModeExt, LAW), c->stream, c->d_blocks,
                        c->d_block_walls,
                        c->d_block_rooms, c->d_walls, (const R *)c->d_T[0], (const R *)c->d_T[1],
                        (const R *)c->d_P[0], (const R *)c->d_P[1], c->d_lay, c->d_rooms,
@@ -598,16 +596,22 @@ void launch_resident(dfhm_ctx *c, int k)
     // zones and radiative sources / links compile into variants of their
     // own, so that runs without them keep the leaner step loop
     const int mode = c->extended ? kModeExt : (c->nr > 0 ? kModeZones : kModePlain);
+#define DFHM_RES_LAW(T_, P_, L_)                                                     \
+    {                                                                                \
+        if (mode == kModeExt) launch_res<R, P_, T_, kModeExt, L_>(c, k);             \
+        else if (mode == kModeZones) launch_res<R, P_, T_, kModeZones, L_>(c, k);    \
+        else launch_res<R, P_, T_, kModePlain, L_>(c, k);                            \
+    }
 #define DFHM_RES_CASE(T_, P_)                                                        \
     if (nt == T_ && npt == P_) {                                                     \
-        if (mode == kModeExt) launch_res<R, P_, T_, kModeExt>(c, k);                 \
-        else if (mode == kModeZones) launch_res<R, P_, T_, kModeZones>(c, k);        \
-        else launch_res<R, P_, T_, kModePlain>(c, k);                                \
+        if (c->cfg.law == DFHM_LAW_TABLE1) DFHM_RES_LAW(T_, P_, 1)                   \
+        else DFHM_RES_LAW(T_, P_, 0)                                                 \
         return;                                                                      \
     }
     DFHM_RES_CASE(256, 4) DFHM_RES_CASE(128, 8) DFHM_RES_CASE(256, 2) DFHM_RES_CASE(512, 2)
     DFHM_RES_CASE(128, 4) DFHM_RES_CASE(512, 4) DFHM_RES_CASE(256, 8)
 #undef DFHM_RES_CASE
+#undef DFHM_RES_LAW
 }
 
 template <typename R>
@@ -746,8 +750,9 @@ dfhm_status dfhm_create(const dfhm_config *cfg, const dfhm_wall *walls, int64_t 
     c->ntiles = (int)tiles.size();
     c->wall_room.assign(n_walls, -1);
     c->room_side.assign(n_walls, 1);
-    // the resident kernel implements the shape law only
-    c->shape_uniform = cfg->law == DFHM_LAW_SHAPE && shape_of(walls, n_walls, c->shape);
+    // the resident kernel needs one shape for the shape law (the Table 1 law
+    // has a fixed one)
+    c->shape_uniform = cfg->law == DFHM_LAW_TABLE1 || shape_of(walls, n_walls, c->shape);
     if (cfg->schedule == DFHM_SCHED_RESIDENT && !c->shape_uniform) {
         delete c;
         return DFHM_E_INVAL;

@@ -280,9 +280,10 @@ __device__ __forceinline__ double t1_psat(double th)
 }
 __device__ __forceinline__ float t1_psat(float th) { return psat_th(th); }
 
-// Conductivities of the Table 1 law at (theta, P) for layer scales m.
+// The Table 1 law's conductivity functions at (theta, P), before the layer
+// scales: (lambda, k_M, L_v delta_v).
 template <typename R>
-__device__ __forceinline__ KCoef<R> t1_law_k(const double *m, R th, R P, R Lv)
+__device__ __forceinline__ KCoef<R> t1_kfun(R th, R P, R Lv)
 {
     const R T = th + (R)273.15;
     const R phi = div_nr(P, t1_psat(th));
@@ -293,12 +294,22 @@ __device__ __forceinline__ KCoef<R> t1_law_k(const double *m, R th, R P, R Lv)
     const R dv = div_nr((R)1.88e-6 * u, T * ((R)0.503 * u * u + (R)0.497));
     // 10^(1.44 - 0.07 log10(2 phi)) = 10^1.44 (2 phi)^(-0.07)
     const R a = (R)2 * phi - (R)2;
-    const R kM = (R)(1.97e-10 * 27.542287033381662) * t1_exp((R)-0.07 * (lnphi + (R)0.69314718055994531)) +
-                 (R)1.77e-7 * t1_exp((R)-8 * a * a);
     KCoef<R> k;
-    k.kT = (R)m[L_K0] * ((R)0.2 + (R)0.0045 * f);
-    k.kM = (R)m[L_KM0] * kM;
-    k.kX = (R)m[L_KM0] * Lv * dv;
+    k.kT = (R)0.2 + (R)0.0045 * f;
+    k.kM = (R)(1.97e-10 * 27.542287033381662) * t1_exp((R)-0.07 * (lnphi + (R)0.69314718055994531)) +
+           (R)1.77e-7 * t1_exp((R)-8 * a * a);
+    k.kX = Lv * dv;
+    return k;
+}
+
+// Conductivities of the Table 1 law at (theta, P) for layer scales m.
+template <typename R>
+__device__ __forceinline__ KCoef<R> t1_law_k(const double *m, R th, R P, R Lv)
+{
+    KCoef<R> k = t1_kfun<R>(th, P, Lv);
+    k.kT *= (R)m[L_K0];
+    k.kM *= (R)m[L_KM0];
+    k.kX *= (R)m[L_KM0];
     return k;
 }
 
