@@ -150,8 +150,11 @@ __device__ __forceinline__ Quad<R> lds_scales(const unsigned char *base, int off
 // per SIMD each).  8 nodes per lane: two waves.  (Measured on the
 // 65,536 x 1001 batch: FP64 2 -> 4 waves +27 %; FP32 with four waves 6 %
 // slower than with three, with five 30 % slower.)
-template <typename R, int NPT, int NT> constexpr int res_waves_per_eu()
+template <typename R, int NPT, int NT, int LAW> constexpr int res_waves_per_eu()
 {
+    // the Table 1 law's FP64 node work is larger: three waves (measured
+    // 1.5 % faster than four on its 65,536 x 1001 batch, two 0.5 % slower)
+    if (LAW == 1 && sizeof(R) == 8 && NPT <= 4) return 3;
     return NPT > 4 ? 2 : (sizeof(R) == 8 || NT > 256 ? 4 : 3);
 }
 
@@ -165,7 +168,7 @@ constexpr int kModeExt = 2;     // radiative sources and / or linked zones
 // same way: k_TT = k0 lambda, k_M = kM0 K, k_TM = kM0 L_v delta_v, so the
 // harmonic interface means of the scale tables still apply).
 template <typename R, int NPT, int NT, int MODE, int LAW>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT>())))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT, LAW>())))
 k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ block_walls,
               const int32_t *__restrict__ block_rooms, const WallDev *__restrict__ walls,
               const R *T0b, const R *T1b, const R *P0b, const R *P1b,
