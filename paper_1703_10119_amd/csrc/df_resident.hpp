@@ -327,7 +327,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
 
     R Ta_[NPT], Pa_[NPT], Tb_[NPT], Pb_[NPT];   // two level buffers (roles alternate)
     int info[NPT];
-    int coff[NPT], koff[NPT];                   // byte offsets of the scale pairs in LDS
+    // LDS byte offsets of a node's capacity and face scale entries, both
+    // 16-byte aligned, packed as 16-byte units in one register (low: capacity,
+    // high: face), so that they stay in registers through the loop
+    uint32_t offs[NPT];
     {
         int slot = 0;
 #pragma unroll
@@ -335,8 +338,8 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             const int b = t * NPT + q;
             Ta_[q] = Pa_[q] = Tb_[q] = Pb_[q] = 0;
             info[q] = kFaceNone << 13;
-            coff[q] = (int)(kWalls + offsetof(WallRec<R>, cc) + sizeof(R) * 4 * 3);
-            koff[q] = (int)(kWalls + offsetof(WallRec<R>, fk) + sizeof(R) * 4 * kFaceNone);
+            offs[q] = (uint32_t)((kWalls + offsetof(WallRec<R>, cc) + sizeof(R) * 4 * 3) >> 4) |
+                      ((uint32_t)((kWalls + offsetof(WallRec<R>, fk) + sizeof(R) * 4 * kFaceNone) >> 4) << 16);
             if (b < B.n_nodes) {
                 while (b >= wr[slot].wend) ++slot;
                 const WallDev &W = walls[wr[slot].wid];
@@ -350,8 +353,9 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 info[q] = slot | ((j == 0) << 8) | ((j == W.nx - 1) << 9) | (1 << 10) | (la << 11) |
                           (fe << 13);
                 const int rb = (int)(kWalls + sizeof(WallRec<R>) * (size_t)slot);
-                coff[q] = rb + (int)(offsetof(WallRec<R>, cc) + sizeof(R) * 4 * la);
-                koff[q] = rb + (int)(offsetof(WallRec<R>, fk) + sizeof(R) * 4 * fe);
+                const uint32_t co = (uint32_t)(rb + (int)(offsetof(WallRec<R>, cc) + sizeof(R) * 4 * la));
+                const uint32_t ko = (uint32_t)(rb + (int)(offsetof(WallRec<R>, fk) + sizeof(R) * 4 * fe));
+                offs[q] = (co >> 4) | ((ko >> 4) << 16);
             }
         }
     }
@@ -467,7 +471,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         R kT[NPT], kM[NPT], phn[NPT], kX[NPT];
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
-            const Quad<R> k0 = lds_scales<R>(lds, koff[q]);
+            const Quad<R> k0 = lds_scales<R>(lds, (int)((offs[q] >> 16) << 4));
             if constexpr (LAW == 1) {
                 // Table 1 law at the face state; a node without a right face
                 // gets zeros (its own state may be padding at 0 K)
@@ -526,7 +530,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
             const int f = info[q];
-            const Quad<R> c0 = lds_scales<R>(lds, coff[q]);
+            const Quad<R> c0 = lds_scales<R>(lds, (int)((offs[q] & 0xffffu) << 4));
             const R pr = c0.p;
             const R th = c0.th + Tn[q];
             R ccT, ccM, ccX, lX, kXq;
