@@ -297,8 +297,15 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
 
     // ---- ambient lanes: one per wall side; the outdoor sinusoids advance by
     // an exact rotation through the chunk, anchored at t^n0 (state in LDS)
-    const bool amb_lane = t < 2 * nwb;
-    const int amb_slot = t >> 1, amb_side = t & 1;
+    // In the walls-only variant they start at the second wave: the first wave
+    // of every workgroup holds a left surface node, and the waves of equal
+    // index of the resident workgroups share a SIMD, so the ambient work
+    // would pile onto one SIMD per CU.  (With zones, measured, the first wave
+    // is the better place.)
+    constexpr int kAmb0 = (MODE == kModePlain && NT >= 64 + 2 * kResMaxWalls) ? 64 : 0;
+    const int ta = t - kAmb0;
+    const bool amb_lane = ta >= 0 && ta < 2 * nwb;
+    const int amb_slot = ta >> 1, amb_side = ta & 1;
     if (amb_lane) {
         const WallDev &W = walls[block_walls[B.w_begin + amb_slot]];
         const double *ST = W.Tamb[amb_side], *SR = W.RHamb[amb_side];
