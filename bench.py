@@ -367,6 +367,7 @@ def main():
             "test_samples": r["samples"], "mlp_seconds": r["mlp_seconds"],
             "df_warm_seconds": r["df_warm_seconds"], "df_cold_seconds": r["df_cold_seconds"],
             "inference_tflops_end_to_end": r["mlp_tflops"], "train_tflops_end_to_end": r["train_tflops"],
+            "ensemble": r["n_nets"],
             "train": {"walls": r["n_train"], "samples_per_epoch": r["n_train"] * S.N_WINDOWS,
                       "epochs": r["epochs"], "batch": r["batch"], "lr": r["lr"],
                       "seconds": r["train_seconds"], "data_seconds": r["data_seconds"]},

@@ -364,6 +364,16 @@ dfhm_status dfhm_mlp_features(const int32_t *wall_dev, const double *t_dev, cons
  * non-positive std or tau. */
 dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scale, float tau,
                             float *flux_dev, uint8_t *fallback_dev, void *stream);
+/* Decode an ensemble of n_nets networks trained on the same targets
+ * (1 <= n_nets <= 4): y_dev is a host array of n_nets device output arrays,
+ * each laid out as for dfhm_mlp_decode.  flux_dev[b][f] is the mean of the
+ * members' u_f exp(l_f), and the predicted error the mean of their
+ * sd(u_f) + |u_f| sd(l_f), compared with tau as there; n_nets = 1 gives
+ * dfhm_mlp_decode's results.  DFHM_E_INVAL as there, and for a null y_dev or
+ * member or n_nets outside [1, 4]. */
+dfhm_status dfhm_mlp_decode_ensemble(const float *const *y_dev, int32_t n_nets, int64_t batch,
+                                     const float *scale, float tau, float *flux_dev,
+                                     uint8_t *fallback_dev, void *stream);
 
 /* Checkpoint / restart.  dfhm_save writes the evolving state of a context —
  * its step index, both levels of every wall in the storage format (FP64

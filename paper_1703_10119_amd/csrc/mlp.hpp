@@ -351,21 +351,36 @@ __global__ void k_features(const int32_t *__restrict__ wall_of, const double *__
 // flux_f = u_f exp(l_f).  The predicted error relative to the RMS flux is
 // e_f = sd(u_f) + |u_f| sd(l_f) to first order, sd = std * exp(s / 2);
 // fallback when e_f > tau for either field.  scale[8] = (mean, std) of
-// u_q, u_g, l_q, l_g.
+// u_q, u_g, l_q, l_g.  With several networks (an ensemble trained on the
+// same targets), flux_f and e_f are the means over the members.
 struct DecodeScale { float m[4], s[4]; };
+constexpr int kMaxEnsemble = 4;
+struct DecodeNets {
+    const float *y[kMaxEnsemble];
+    int n;
+};
 
-__global__ void k_decode(const float *__restrict__ y, int64_t batch, DecodeScale sc, float tau,
+__global__ void k_decode(DecodeNets nets, int64_t batch, DecodeScale sc, float tau,
                          float *__restrict__ flux, uint8_t *__restrict__ fallback)
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
-    const float *o = y + 8 * b;
+    const float inv = 1.0f / (float)nets.n;
     bool fb = false;
     for (int f = 0; f < 2; ++f) {
-        const float u = o[f] * sc.s[f] + sc.m[f];
-        const float lg = o[2 + f] * sc.s[2 + f] + sc.m[2 + f];
-        flux[2 * b + f] = u * __expf(lg);
-        const float e = sc.s[f] * __expf(0.5f * o[4 + f]) + fabsf(u) * sc.s[2 + f] * __expf(0.5f * o[6 + f]);
+        float fl = 0.f, e = 0.f;
+#pragma unroll
+        for (int k = 0; k < kMaxEnsemble; ++k) {
+            if (k < nets.n) {
+                const float *o = nets.y[k] + 8 * b;
+                const float u = o[f] * sc.s[f] + sc.m[f];
+                const float lg = o[2 + f] * sc.s[2 + f] + sc.m[2 + f];
+                fl += u * __expf(lg);
+                e += sc.s[f] * __expf(0.5f * o[4 + f]) + fabsf(u) * sc.s[2 + f] * __expf(0.5f * o[6 + f]);
+            }
+        }
+        flux[2 * b + f] = fl * inv;
+        e *= inv;
         fb = fb || !(e <= tau);
     }
     fallback[b] = (uint8_t)fb;

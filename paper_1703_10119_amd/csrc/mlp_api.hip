@@ -382,11 +382,12 @@ dfhm_status dfhm_mlp_features(const int32_t *wall_dev, const double *t_dev, cons
     return hipGetLastError() == hipSuccess ? DFHM_OK : DFHM_E_DEVICE;
 }
 
-dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scale, float tau,
-                            float *flux_dev, uint8_t *fallback_dev, void *stream)
+static dfhm_status decode_nets(const DecodeNets &nets, int64_t batch, const float *scale, float tau,
+                               float *flux_dev, uint8_t *fallback_dev, void *stream)
 {
-    if (!y_dev || !scale || !flux_dev || !fallback_dev || batch < 0 || !(tau > 0.f))
-        return DFHM_E_INVAL;
+    if (!scale || !flux_dev || !fallback_dev || batch < 0 || !(tau > 0.f)) return DFHM_E_INVAL;
+    for (int k = 0; k < nets.n; ++k)
+        if (!nets.y[k]) return DFHM_E_INVAL;
     if (batch == 0) return DFHM_OK;
     DecodeScale sc;
     for (int i = 0; i < 4; ++i) {
@@ -395,8 +396,28 @@ dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scal
         if (!std::isfinite(sc.m[i]) || !(sc.s[i] > 0.f) || !std::isfinite(sc.s[i])) return DFHM_E_INVAL;
     }
     hipLaunchKernelGGL(k_decode, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)stream, y_dev, batch, sc, tau, flux_dev, fallback_dev);
+                       (hipStream_t)stream, nets, batch, sc, tau, flux_dev, fallback_dev);
     return hipGetLastError() == hipSuccess ? DFHM_OK : DFHM_E_DEVICE;
+}
+
+dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scale, float tau,
+                            float *flux_dev, uint8_t *fallback_dev, void *stream)
+{
+    DecodeNets nets{};
+    nets.y[0] = y_dev;
+    nets.n = 1;
+    return decode_nets(nets, batch, scale, tau, flux_dev, fallback_dev, stream);
+}
+
+dfhm_status dfhm_mlp_decode_ensemble(const float *const *y_dev, int32_t n_nets, int64_t batch,
+                                     const float *scale, float tau, float *flux_dev,
+                                     uint8_t *fallback_dev, void *stream)
+{
+    if (!y_dev || n_nets < 1 || n_nets > kMaxEnsemble) return DFHM_E_INVAL;
+    DecodeNets nets{};
+    for (int k = 0; k < n_nets; ++k) nets.y[k] = y_dev[k];
+    nets.n = n_nets;
+    return decode_nets(nets, batch, scale, tau, flux_dev, fallback_dev, stream);
 }
 
 const char *dfhm_mlp_last_error(const dfhm_mlp *m) { return m ? m->err.c_str() : "null network"; }

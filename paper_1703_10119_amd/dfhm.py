@@ -115,7 +115,7 @@ EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_zone_lin
            "dfhm_mlp_create", "dfhm_mlp_param_count", "dfhm_mlp_get_params",
            "dfhm_mlp_set_params", "dfhm_mlp_forward", "dfhm_mlp_gradients",
            "dfhm_mlp_train_step", "dfhm_mlp_last_error", "dfhm_mlp_destroy",
-           "dfhm_mlp_features", "dfhm_mlp_decode")
+           "dfhm_mlp_features", "dfhm_mlp_decode", "dfhm_mlp_decode_ensemble")
 
 _lib = None
 
@@ -188,9 +188,10 @@ def load(path: str = LIB_PATH):
     L.dfhm_mlp_destroy.argtypes = [P]
     L.dfhm_mlp_features.argtypes = [P, P, P, P, I64, C.POINTER(FeatureDesc), P, P]
     L.dfhm_mlp_decode.argtypes = [P, I64, P, C.c_float, P, P, P]
+    L.dfhm_mlp_decode_ensemble.argtypes = [P, I32, I64, P, C.c_float, P, P, P]
     for f in (L.dfhm_mlp_create, L.dfhm_mlp_get_params, L.dfhm_mlp_set_params,
               L.dfhm_mlp_forward, L.dfhm_mlp_gradients, L.dfhm_mlp_train_step,
-              L.dfhm_mlp_features, L.dfhm_mlp_decode):
+              L.dfhm_mlp_features, L.dfhm_mlp_decode, L.dfhm_mlp_decode_ensemble):
         f.restype = C.c_int
     _lib = L
     return L

@@ -242,9 +242,11 @@ def train(net, data, walls, desc, targets, epochs=3, batch=8192, lr=1e-3, seed=0
     return dict(losses=losses, seconds=time.perf_counter() - t0, steps=steps, samples=steps * batch)
 
 
-def predict(net, walls, t_windows, desc, targets, tau, batch=65536):
-    """Network fluxes [W, K, 2] and fallback flags [W, K] for all windows."""
+def predict(nets, walls, t_windows, desc, targets, tau, batch=65536):
+    """Network fluxes [W, K, 2] and fallback flags [W, K] for all windows,
+    from one network or the mean of an ensemble (a list of networks)."""
     import torch
+    nets = list(nets) if isinstance(nets, (list, tuple)) else [nets]
     dev = "cuda"
     sines, params = wall_inputs(walls)
     sines_d = torch.tensor(sines, device=dev)
@@ -261,11 +263,13 @@ def predict(net, walls, t_windows, desc, targets, tau, batch=65536):
     for b0 in range(0, n, batch):
         b1 = min(n, b0 + batch)
         x = features(wall_of[b0:b1].contiguous(), t_of[b0:b1].contiguous(), sines_d, params_d, desc)
-        y = net.forward(x)
-        st = _lib().dfhm_mlp_decode(y.data_ptr(), b1 - b0, sc.ctypes.data_as(C.c_void_p),
-                                    float(tau), flux[b0:].data_ptr(), fb[b0:].data_ptr(), _stream())
+        ys = [net.forward(x) for net in nets]
+        ptrs = (C.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
+        st = _lib().dfhm_mlp_decode_ensemble(ptrs, len(ys), b1 - b0,
+                                             sc.ctypes.data_as(C.c_void_p), float(tau),
+                                             flux[b0:].data_ptr(), fb[b0:].data_ptr(), _stream())
         if st != 0:
-            raise dfhm.DfhmError(st, "dfhm_mlp_decode")
+            raise dfhm.DfhmError(st, "dfhm_mlp_decode_ensemble")
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     return (flux.cpu().numpy().reshape(W, K, 2).astype(np.float64),
@@ -278,11 +282,11 @@ def errors(pred, truth):
     return np.abs(pred - truth) / rms
 
 
-def calibrate_tau(net, walls, data, desc, targets, target=0.01, q=0.99):
+def calibrate_tau(nets, walls, data, desc, targets, target=0.01, q=0.99):
     """Largest fallback threshold (predicted relative error) whose p-q error
     after fallback is <= target on the given (calibration) walls."""
     for tau in np.geomspace(0.1, 0.0005, 40):
-        pred, fb, _ = predict(net, walls, data["t"], desc, targets, tau)
+        pred, fb, _ = predict(nets, walls, data["t"], desc, targets, tau)
         e = errors(pred, data["flux"]).max(axis=2)
         e[fb] = 0.0                      # fallback samples are the DF solve itself
         if np.quantile(e, q) <= target:
@@ -291,10 +295,13 @@ def calibrate_tau(net, walls, data, desc, targets, target=0.01, q=0.99):
 
 
 def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=16384,
-          target=0.01, q=0.99, cal_margin=0.9, seed=1, act_pairs=False, log=None):
+          target=0.01, q=0.99, cal_margin=0.9, seed=1, act_pairs=False, n_nets=2, log=None):
     """Train on DF histories, calibrate the fallback threshold on one set of
     walls and measure error and speed-up on another (all C2-type walls:
-    30 cm, 1001 nodes, dt = 1 s, different generator seeds).
+    30 cm, 1001 nodes, dt = 1 s, different generator seeds).  With n_nets > 1
+    an ensemble of networks (seeds seed, seed + 1, ...) is trained on the
+    same data and its mean flux and mean predicted error are used; the MLP
+    time then covers every member.
 
     Error: |q_MLP - q_DF| / RMS over the windows of q_DF, per wall and
     field; a sample's error is the larger of its two fields, and fallback
@@ -316,12 +323,16 @@ def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=1638
     targets = Targets(d_tr["flux"])
     _, params = wall_inputs(tr)
     desc = feature_desc(params, d_tr["t"][0], d_tr["t"][-1])
-    net = MLP(max_batch=65536, seed=seed, act_pairs=act_pairs)
-    fit = train(net, d_tr, tr, desc, targets, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
+    nets = [MLP(max_batch=65536, seed=seed + k, act_pairs=act_pairs) for k in range(n_nets)]
+    fits = [train(net, d_tr, tr, desc, targets, epochs=epochs, batch=batch, lr=lr, seed=seed + k,
+                  log=log) for k, net in enumerate(nets)]
+    fit = dict(steps=sum(f["steps"] for f in fits), seconds=sum(f["seconds"] for f in fits),
+               samples=sum(f["samples"] for f in fits))
+    n_params = nets[0].n_params
     say(f"trained {fit['steps']} steps of {batch} in {fit['seconds']:.1f} s")
-    tau = calibrate_tau(net, ca, d_ca, desc, targets, target=cal_margin * target, q=q)
-    predict(net, te, d_te["t"], desc, targets, 10.0)            # warm-up
-    pred, fb, mlp_s = predict(net, te, d_te["t"], desc, targets, tau if tau else 1e-30)
+    tau = calibrate_tau(nets, ca, d_ca, desc, targets, target=cal_margin * target, q=q)
+    predict(nets, te, d_te["t"], desc, targets, 10.0)           # warm-up
+    pred, fb, mlp_s = predict(nets, te, d_te["t"], desc, targets, tau if tau else 1e-30)
     e_raw = errors(pred, d_te["flux"]).max(axis=2)
     e = e_raw.copy()
     e[fb] = 0.0
@@ -335,8 +346,9 @@ def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=1638
     cold_sample = per_update * nodes * cold_steps
     df_warm = n_samp * warm_sample
     df_cold = n_samp * cold_sample
-    flops = 2.0 * net.n_params * n_samp          # multiply-adds of the forward pass
-    net.close()
+    flops = 2.0 * n_params * n_samp * n_nets     # multiply-adds of the forward passes
+    for net in nets:
+        net.close()
     return dict(
         tau=tau, fallback_fraction=f, samples=n_samp,
         err_p50=float(np.median(e)), err_p99=float(np.quantile(e, q)), err_max=float(e.max()),
@@ -347,9 +359,9 @@ def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=1638
         speedup_cold=df_cold / (mlp_s + f * df_cold),
         speedup_no_fallback_warm=df_warm / mlp_s,
         train_seconds=fit["seconds"], train_samples=fit["samples"],
-        train_tflops=3.0 * 2.0 * net.n_params * fit["samples"] / fit["seconds"] / 1e12,
+        train_tflops=3.0 * 2.0 * n_params * fit["samples"] / fit["seconds"] / 1e12,
         data_seconds=d_tr["df_seconds"], n_train=n_train, n_cal=n_cal, n_test=n_test,
-        epochs=epochs, batch=batch, lr=lr)
+        epochs=epochs, batch=batch, lr=lr, n_nets=n_nets)
 
 
 def kernel_bench(batch=65536, train_batch=16384, iters=50, act_pairs=False, seed=0):

@@ -241,6 +241,70 @@ def test_decode_and_fallback_flags():
                                        flux.data_ptr(), fb.data_ptr(), None) == 1
 
 
+def test_decode_ensemble_is_the_member_mean():
+    """Ensemble decode against its definition: flux and predicted error are
+    the means of the members' values; one member gives dfhm_mlp_decode's
+    results bit for bit; bad member counts or a null member are refused."""
+    dev = _dev()
+    rng = np.random.default_rng(17)
+    B, K = 777, 3
+    ys = []
+    for _ in range(K):
+        y = rng.normal(0, 1, (B, 8)).astype(np.float32)
+        y[:, 4:] = rng.uniform(-20, -4, (B, 4))
+        ys.append(y)
+    scale = np.array([0.1, 1.2, -0.3, 0.9, 1.0, 0.5, -14.0, 0.8], np.float32)
+    tau = 0.01
+    L = dfhm.load()
+    st_ = torch.cuda.current_stream().cuda_stream
+    yd = [torch.tensor(y, device=dev) for y in ys]
+    ptrs = (C.c_void_p * K)(*[t.data_ptr() for t in yd])
+    flux = torch.empty((B, 2), dtype=torch.float32, device=dev)
+    fb = torch.empty(B, dtype=torch.uint8, device=dev)
+    assert L.dfhm_mlp_decode_ensemble(ptrs, K, B, scale.ctypes.data_as(C.c_void_p), tau,
+                                      flux.data_ptr(), fb.data_ptr(), st_) == 0
+    torch.cuda.synchronize()
+    m, sd = scale[0::2].astype(np.float64), scale[1::2].astype(np.float64)
+    want = np.zeros((B, 2))
+    e = np.zeros((B, 2))
+    bound = np.zeros((B, 2))
+    for y in ys:
+        yv = y.astype(np.float64)
+        u = yv[:, :2] * sd[:2] + m[:2]
+        lg = yv[:, 2:4] * sd[2:] + m[2:]
+        want += u * np.exp(lg) / K
+        e += (sd[:2] * np.exp(0.5 * yv[:, 4:6]) + np.abs(u) * sd[2:] * np.exp(0.5 * yv[:, 6:8])) / K
+        bound += (1e-6 * (np.abs(yv[:, :2] * sd[:2]) + np.abs(m[:2])) * np.exp(lg)
+                  + 1e-5 * np.abs(u * np.exp(lg))) / K
+    f = flux.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(f - want) <= bound + 1e-6 * np.abs(want))
+    flag = np.any(e > tau, axis=1)
+    clear = np.all(np.abs(e / tau - 1) > 1e-4, axis=1)
+    got = fb.cpu().numpy().astype(bool)
+    assert 0.05 < flag.mean() < 0.95
+    assert np.array_equal(got[clear], flag[clear])
+    # one member = dfhm_mlp_decode, bit for bit
+    one = (C.c_void_p * 1)(yd[1].data_ptr())
+    f1 = torch.empty((B, 2), dtype=torch.float32, device=dev)
+    b1 = torch.empty(B, dtype=torch.uint8, device=dev)
+    f2 = torch.empty((B, 2), dtype=torch.float32, device=dev)
+    b2 = torch.empty(B, dtype=torch.uint8, device=dev)
+    assert L.dfhm_mlp_decode_ensemble(one, 1, B, scale.ctypes.data_as(C.c_void_p), tau,
+                                      f1.data_ptr(), b1.data_ptr(), st_) == 0
+    assert L.dfhm_mlp_decode(yd[1].data_ptr(), B, scale.ctypes.data_as(C.c_void_p), tau,
+                             f2.data_ptr(), b2.data_ptr(), st_) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2) and torch.equal(b1, b2)
+    for n in (0, 5):
+        assert L.dfhm_mlp_decode_ensemble(ptrs, n, B, scale.ctypes.data_as(C.c_void_p), tau,
+                                          flux.data_ptr(), fb.data_ptr(), st_) == 1
+    holed = (C.c_void_p * 2)(yd[0].data_ptr(), None)
+    assert L.dfhm_mlp_decode_ensemble(holed, 2, B, scale.ctypes.data_as(C.c_void_p), tau,
+                                      flux.data_ptr(), fb.data_ptr(), st_) == 1
+    assert L.dfhm_mlp_decode_ensemble(None, 2, B, scale.ctypes.data_as(C.c_void_p), tau,
+                                      flux.data_ptr(), fb.data_ptr(), st_) == 1
+
+
 def test_mlp_argument_errors():
     _dev()
     from paper_1703_10119_amd import surrogate as S
