@@ -9,9 +9,10 @@ the timed region; the start-up step runs in the warm-up.
 
 Prints one JSON line (value = FP64 cell-updates/s; the FP32 run of the same
 batch is reported under "fp32").  The surface-flux surrogate is measured
-after the DF runs ("surrogate"): trained on 65,536 walls x 156 windows of DF
-histories (about 10 M samples), its fallback threshold calibrated on 2,048
-other walls, error and speed-up measured on 4,096 more.
+after the DF runs ("surrogate"): an ensemble of two networks trained on
+65,536 walls x 156 windows of DF histories (about 10 M samples), its fallback
+threshold calibrated on 2,048 other walls, error and speed-up measured on
+4,096 more.
 """
 from __future__ import annotations
 
