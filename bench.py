@@ -9,7 +9,7 @@ the timed region; the start-up step runs in the warm-up.
 
 Prints one JSON line (value = FP64 cell-updates/s; the FP32 run of the same
 batch is reported under "fp32").  The surface-flux surrogate is measured
-after the DF runs ("surrogate"): an ensemble of two networks trained on
+after the DF runs ("surrogate"): an ensemble of three networks trained on
 65,536 walls x 156 windows of DF histories (about 10 M samples), its fallback
 threshold calibrated on 2,048 other walls, error and speed-up measured on
 4,096 more.
@@ -350,7 +350,10 @@ def main():
                        "finite": fin32}
     if not a.no_surrogate:
         from paper_1703_10119_amd import surrogate as S
-        r = S.study(epochs=a.surrogate_epochs)
+        # progress of the study's phases and training (stderr; the result
+        # line alone goes to stdout)
+        r = S.study(epochs=a.surrogate_epochs,
+                    log=lambda *m: print(*m, file=sys.stderr, flush=True))
         kb = S.kernel_bench()
         out["surrogate"] = {
             "roofline": {"bound": "mfma", "achieved": round(kb["forward_tflops"], 2),

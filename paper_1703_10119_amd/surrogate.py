@@ -235,7 +235,7 @@ def train(net, data, walls, desc, targets, epochs=3, batch=8192, lr=1e-3, seed=0
             loss = net.train_step(x, y, cur, want_loss=want)
             if want:
                 losses.append((k, loss))
-                if log:
+                if log and (k % 2000 == 0 or k == steps - 1):
                     log(f"  step {k}/{steps} loss {loss:.4f}")
             k += 1
     torch.cuda.synchronize()
@@ -295,7 +295,7 @@ def calibrate_tau(nets, walls, data, desc, targets, target=0.01, q=0.99):
 
 
 def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=16384,
-          target=0.01, q=0.99, cal_margin=0.9, seed=1, act_pairs=False, n_nets=2, log=None):
+          target=0.01, q=0.99, cal_margin=0.9, seed=1, act_pairs=False, n_nets=3, log=None):
     """Train on DF histories, calibrate the fallback threshold on one set of
     walls and measure error and speed-up on another (all C2-type walls:
     30 cm, 1001 nodes, dt = 1 s, different generator seeds).  With n_nets > 1
@@ -324,12 +324,16 @@ def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=1638
     _, params = wall_inputs(tr)
     desc = feature_desc(params, d_tr["t"][0], d_tr["t"][-1])
     nets = [MLP(max_batch=65536, seed=seed + k, act_pairs=act_pairs) for k in range(n_nets)]
-    fits = [train(net, d_tr, tr, desc, targets, epochs=epochs, batch=batch, lr=lr, seed=seed + k,
-                  log=log) for k, net in enumerate(nets)]
+    fits = []
+    for k, net in enumerate(nets):
+        say(f"training network {k + 1} of {n_nets}")
+        fits.append(train(net, d_tr, tr, desc, targets, epochs=epochs, batch=batch, lr=lr,
+                          seed=seed + k, log=log))
     fit = dict(steps=sum(f["steps"] for f in fits), seconds=sum(f["seconds"] for f in fits),
                samples=sum(f["samples"] for f in fits))
     n_params = nets[0].n_params
     say(f"trained {fit['steps']} steps of {batch} in {fit['seconds']:.1f} s")
+    say("calibrating the fallback threshold")
     tau = calibrate_tau(nets, ca, d_ca, desc, targets, target=cal_margin * target, q=q)
     predict(nets, te, d_te["t"], desc, targets, 10.0)           # warm-up
     pred, fb, mlp_s = predict(nets, te, d_te["t"], desc, targets, tau if tau else 1e-30)

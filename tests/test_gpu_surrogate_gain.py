@@ -1,7 +1,7 @@
 """What the trained surrogate gains over the DF solve without it (GPU).
 
 A reduced version of the full study (16,384 training walls instead of
-65,536): train the networks (an ensemble of two) on DF histories with the
+65,536): train the networks (an ensemble of three) on DF histories with the
 project's kernels, calibrate the fallback threshold on one set of walls,
 then on a third set
 check that the error after fallback meets the 1 % target at the 99th
