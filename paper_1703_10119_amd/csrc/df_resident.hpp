@@ -153,9 +153,11 @@ __device__ __forceinline__ Quad<R> lds_scales(const unsigned char *base, int off
 template <typename R, int NPT, int NT, int LAW> constexpr int res_waves_per_eu()
 {
     // the Table 1 law's FP64 node work is larger: three waves (measured
-    // 1.5 % faster than four on its 65,536 x 1001 batch, two 0.5 % slower)
+    // 1.5 % faster than four on its 65,536 x 1001 batch, two 0.5 % slower);
+    // otherwise four for up to 4 nodes per lane, FP32 included (measured
+    // against three: +6 % on the 65,536 x 1001 batch, +2-4 % with zones)
     if (LAW == 1 && sizeof(R) == 8 && NPT <= 4) return 3;
-    return NPT > 4 ? 2 : (sizeof(R) == 8 || NT > 256 ? 4 : 3);
+    return NPT > 4 ? 2 : 4;
 }
 
 // Kernel variants: only what a launch needs is compiled in, since every
