@@ -140,37 +140,40 @@ __device__ __forceinline__ Quad<R> lds_scales(const unsigned char *base, int off
     return q;
 }
 
-// Register budget (waves per SIMD).  FP64 with up to 4 nodes per lane: four
-// waves (at most 128 VGPRs; the few loop-invariant values that do not fit
-// are re-read from the L1-resident spill area each step, which costs far
-// less than the waves that hide the latency of the FP64 pipeline and of
-// LDS).  FP32 issues at the VALU peak already and is sensitive to spill
-// traffic: three waves (168 VGPRs) where whole workgroups still fill them
-// (up to 256 lanes, one wave per SIMD each), four for 512 lanes (two waves
-// per SIMD each).  8 nodes per lane: two waves.  (Measured on the
-// 65,536 x 1001 batch: FP64 2 -> 4 waves +27 %; FP32 with four waves 6 %
-// slower than with three, with five 30 % slower.)
-template <typename R, int NPT, int NT, int LAW> constexpr int res_waves_per_eu()
-{
-    // the Table 1 law's FP64 node work is larger: three waves (measured
-    // 1.5 % faster than four on its 65,536 x 1001 batch, two 0.5 % slower);
-    // otherwise four for up to 4 nodes per lane, FP32 included (measured
-    // against three: +6 % on the 65,536 x 1001 batch, +2-4 % with zones)
-    if (LAW == 1 && sizeof(R) == 8 && NPT <= 4) return 3;
-    return NPT > 4 ? 2 : 4;
-}
-
+// Register budget (waves per SIMD).  Up to 4 nodes per lane: four waves
+// (at most 128 VGPRs; the few loop-invariant values that do not fit are
+// re-read from the L1-resident spill area each step, which costs far less
+// than the waves that hide the latency of the FP64 pipeline and of LDS),
+// except where the FP64 step carries more code (the Table 1 law, zones):
+// three.  8 nodes per lane: two waves.  (Measured on the 65,536 x 1001
+// batch: FP64 2 -> 4 waves +27 %.  FP32 once measured 6 % slower with four
+// waves than with three; after the ambient lanes left the first wave it is
+// 6 % faster.)
 // Kernel variants: only what a launch needs is compiled in, since every
 // extra line of the step loop competes for the registers of the node work.
 constexpr int kModePlain = 0;   // walls without zones or radiative sources
 constexpr int kModeZones = 1;   // zones coupled to walls
 constexpr int kModeExt = 2;     // radiative sources and / or linked zones
+
+template <typename R, int NPT, int NT, int MODE, int LAW> constexpr int res_waves_per_eu()
+{
+    // the Table 1 law's FP64 node work is larger: three waves (measured
+    // 1.5 % faster than four on its 65,536 x 1001 batch, two 0.5 % slower);
+    // so is the FP64 zone and extended code: three in workgroups of up to 256
+    // lanes (measured against four: +7 % on the building batch, +11 % with
+    // radiation; 512-lane workgroups would lose one of two per CU); otherwise
+    // four for up to 4 nodes per lane, FP32 included (measured against three:
+    // +6 % on the 65,536 x 1001 batch, +2-4 % with zones)
+    if (sizeof(R) == 8 && NPT <= 4 && (LAW == 1 || (MODE != kModePlain && NT <= 256))) return 3;
+    return NPT > 4 ? 2 : 4;
+}
+
 // LAW: 0 = the shape law (scales x the launch's common shape factors),
 // 1 = the Table 1 law (scales x that material's functions, which factor the
 // same way: k_TT = k0 lambda, k_M = kM0 K, k_TM = kM0 L_v delta_v, so the
 // harmonic interface means of the scale tables still apply).
 template <typename R, int NPT, int NT, int MODE, int LAW>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT, LAW>())))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT, MODE, LAW>())))
 k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ block_walls,
               const int32_t *__restrict__ block_rooms, const WallDev *__restrict__ walls,
               const R *T0b, const R *T1b, const R *P0b, const R *P1b,
