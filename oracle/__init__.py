@@ -75,9 +75,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = C.CDLL(_LIB)
+        # DFHM_REF_LIB names another build of dfhm_ref.c: the mutation tests
+        # load copies of the oracle with a planted mistake this way
+        path = os.environ.get("DFHM_REF_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(path):
+                build()
+        L = C.CDLL(path)
         P = C.c_void_p
         L.ref_create.restype = P
         L.ref_create.argtypes = [C.POINTER(_Cfg), C.POINTER(_Wall), C.c_int64,

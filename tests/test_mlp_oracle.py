@@ -117,3 +117,38 @@ def test_bf16_pairs_approach_fp64():
     hi = mlp_ref.bf16(g)
     lo = mlp_ref.bf16(g - hi)
     assert np.all(np.abs(hi + lo - g) <= 2.0 ** -16 * np.abs(g))
+
+
+# GELU(z) = z Phi(z) with the standard normal CDF Phi, and its derivative
+# Phi(z) + z phi(z): Phi(1) = 0.8413447460685429, phi(1) = 0.24197072451914337
+# (textbook values of the normal distribution).
+GELU_POINTS = [(1.0, 0.8413447460685429, 0.8413447460685429 + 0.24197072451914337),
+               (-1.0, -0.15865525393145707, 0.15865525393145707 - 0.24197072451914337),
+               (0.0, 0.0, 0.5),
+               (2.0, 2.0 * 0.9772498680518208, 0.9772498680518208 + 2.0 * 0.05399096651318806)]
+
+
+def _gelu_pins(gelu, gelu_d):
+    for z, g, d in GELU_POINTS:
+        assert abs(float(gelu(np.float64(z))) - g) <= 1e-15 * max(1.0, abs(g)), (z, gelu(z), g)
+        assert abs(float(gelu_d(np.float64(z))) - d) <= 1e-15 * max(1.0, abs(d)), (z, gelu_d(z), d)
+
+
+def test_gelu_at_literal_points():
+    """The erf-form GELU and its derivative at points where the normal CDF
+    and density are known."""
+    _gelu_pins(mlp_ref.gelu, mlp_ref.gelu_d)
+
+
+def test_tanh_form_gelu_fails_the_pins():
+    """A planted mistake: the tanh approximation of GELU (off by 1.5e-4 at
+    z = 1) must fail the literal pins."""
+    import math
+
+    import pytest
+
+    def tanh_gelu(z):
+        return 0.5 * z * (1 + np.tanh(math.sqrt(2 / math.pi) * (z + 0.044715 * z ** 3)))
+
+    with pytest.raises(AssertionError):
+        _gelu_pins(tanh_gelu, mlp_ref.gelu_d)
