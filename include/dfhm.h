@@ -159,9 +159,14 @@ typedef struct {
     int32_t law;            /* DFHM_LAW_* */
 } dfhm_config;
 
-/* Device bytes the wall state of a batch needs (levels, node layer ids,
- * descriptors, flux state, tile tables).  Pass at least this much as the
- * arena of dfhm_create to keep all wall state in caller-owned memory. */
+/* Device bytes the wall state of a batch needs: the two stored time levels of
+ * T and Pv of the three-level scheme (eq. dufort, Sec. 3.1: level n+1 is
+ * written over level n-1), node layer ids, descriptors, flux state and tile
+ * tables.  Pass at least this much as the arena of dfhm_create to keep all
+ * wall state in caller-owned memory.  Zone state is not part of the arena
+ * (so this takes no zone count): zones are coupled after dfhm_create, by
+ * dfhm_room_couple, which allocates their few bytes per zone itself.
+ * Returns 0 when cfg or walls is NULL or n_walls < 1. */
 size_t dfhm_arena_bytes(const dfhm_config *cfg, const dfhm_wall *walls, int64_t n_walls);
 
 /* Create a batch of n_walls >= 1 walls at their initial state (step index 0).
@@ -207,22 +212,35 @@ typedef struct {
  * DFHM_E_STATE (not at step 0, or links set before). */
 dfhm_status dfhm_zone_links(dfhm_ctx *ctx, const dfhm_zone_link *links, int64_t n_links);
 
-/* Queue n_steps >= 0 time steps (asynchronous on the context stream). */
+/* Queue n_steps >= 0 time steps (asynchronous on the context stream).  One
+ * step is the nonlinear Dufort-Frankel update of Sec. 3.1 (eqs. DF_NL,
+ * DF_NL_RHS; coefficients at level n, faces at the face-averaged state),
+ * moisture first and heat with the new vapour pressure (App. A, eqs. DF_eq1,
+ * DF_eq2b), the surface nodes with the DF-averaged surface value (eq. bc_v),
+ * the outdoor air at t^n, and the zones advanced explicitly from level-n
+ * surfaces (Sec. 5.3, eq. wbse_tn_exp).  The first step from step index 0
+ * is the start-up step of dfhm_config.startup.  Errors: DFHM_E_INVAL for
+ * n_steps < 0 or a resident group beyond the launch shape's limits,
+ * DFHM_E_STATE while a non-finite state is latched, DFHM_E_DEVICE. */
 dfhm_status dfhm_step_n(dfhm_ctx *ctx, int64_t n_steps);
 
 /* Wait for queued work; DFHM_E_NONFINITE if a finished step produced a
  * non-finite value (the context then latches DFHM_E_STATE). */
 dfhm_status dfhm_sync(dfhm_ctx *ctx);
 
-/* Surface fluxes, host arrays [n_walls][2 sides][2 fields (heat, vapour)]:
+/* Surface fluxes of the boundary condition eq. (2.3) (HAM_BC) as the scheme
+ * applies them (eq. bc_v), host arrays [n_walls][2 sides][2 fields (heat,
+ * vapour)]:
  * now = the flux applied by the most recent step (DF-averaged surface value,
  * ambient at t^n; for the forward-Euler start-up step the mean over its
  * sub-steps); integral = dt * sum over completed steps, Neumaier-compensated
  * in FP64 (J/m2, kg/m2).  Either pointer may be NULL.  Synchronises. */
 dfhm_status dfhm_fluxes(dfhm_ctx *ctx, double *now, double *integral);
 
-/* Fields of one wall at level 0 (= t^n) or 1 (= t^{n-1}) as FP64 host arrays
- * of nx values (absolute K and Pa, also on the FP32 path).  Synchronises. */
+/* Fields of one wall at level 0 (= t^n) or 1 (= t^{n-1}) of the three-level
+ * scheme (eq. dufort) as FP64 host arrays of nx values (absolute K and Pa,
+ * also on the FP32 path).  Synchronises.  DFHM_E_INVAL for a wall or level
+ * out of range or a NULL array. */
 dfhm_status dfhm_get_fields(dfhm_ctx *ctx, int64_t wall, int level, double *T, double *Pv);
 /* All walls concatenated in wall order (sum of nx values each). */
 dfhm_status dfhm_get_all_fields(dfhm_ctx *ctx, int level, double *T, double *Pv);
@@ -233,7 +251,9 @@ dfhm_status dfhm_set_fields(dfhm_ctx *ctx, int64_t wall, int level, const double
  * n >= 1 makes the next step a DF step). */
 dfhm_status dfhm_set_step_index(dfhm_ctx *ctx, int64_t n);
 
-/* Zone air at level n: Ta [K], Pva [Pa], host arrays of n_rooms. */
+/* Zone air at level n (the state of eq. LAV_equation, Sec. 5.1): Ta [K],
+ * Pva [Pa], host arrays of n_rooms.  Synchronises; DFHM_E_STATE without
+ * zones. */
 dfhm_status dfhm_get_rooms(dfhm_ctx *ctx, double *Ta, double *Pva);
 
 /* Resolved launch configuration (after autotuning). */
@@ -307,10 +327,6 @@ typedef struct {
     int32_t depth;         /* hidden layers, 1..16 */
     int32_t n_out;         /* outputs, 1..32 (training needs an even count) */
     int32_t max_batch;     /* largest batch of one call, <= 4,194,304 */
-    int32_t act_pairs;     /* 0: hidden activations in BF16; 1: as BF16 pairs
-                              hi + lo (16 significant bits; the GEMMs after
-                              the first see them as 2 x width inputs against
-                              duplicated BF16 weights, twice the MFMA work) */
     uint64_t seed;         /* weight initialisation (normal, std sqrt(2/fan_in)) */
     float beta1, beta2, eps, weight_decay;   /* AdamW */
     void *stream;          /* hipStream_t or NULL */
@@ -322,8 +338,20 @@ int64_t dfhm_mlp_param_count(const dfhm_mlp *m);
  * then b[n_out_l]; FP32 host arrays of dfhm_mlp_param_count values. */
 dfhm_status dfhm_mlp_get_params(dfhm_mlp *m, float *host);
 dfhm_status dfhm_mlp_set_params(dfhm_mlp *m, const float *host);
-/* y_dev[batch][n_out] (FP32) = network(x_dev[batch][n_in] BF16). */
+/* y_dev[batch][n_out] (FP32) = network(x_dev[batch][n_in] BF16).  Keeps
+ * every hidden activation and pre-activation in the network's buffers. */
 dfhm_status dfhm_mlp_forward(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, float *y_dev);
+
+/* Stored intermediates of the last forward / gradients pass, for checking
+ * them layer by layer: kind ACT = the BF16 GELU output of hidden layer
+ * `layer` (0 <= layer < depth), PRE = its BF16 pre-activation, DZ = the BF16
+ * loss gradient with respect to the pre-activation of layer `layer` (0 <=
+ * layer <= depth; the output layer's rows are padded to 32 columns), after a
+ * gradients or training pass.  Copies rows x columns values to host
+ * (row-major); synchronises.  DFHM_E_INVAL for a bad kind, layer or rows. */
+enum { DFHM_MLP_ACT = 0, DFHM_MLP_PRE = 1, DFHM_MLP_DZ = 2 };
+dfhm_status dfhm_mlp_get_intermediate(dfhm_mlp *m, int32_t kind, int32_t layer, int64_t rows,
+                                      uint16_t *host);
 /* Training loss for n_out = 2F outputs (means mu_f, then log variances s_f,
  * f < F) and targets y_dev[batch][F] (FP32):
  * L = mean_b sum_f [ r^2 + sg(r^2) exp(-s_f) + s_f ], r = y_f - mu_f,
@@ -375,16 +403,32 @@ dfhm_status dfhm_mlp_decode_ensemble(const float *const *y_dev, int32_t n_nets, 
                                      const float *scale, float tau, float *flux_dev,
                                      uint8_t *fallback_dev, void *stream);
 
+/* Inference of the flux head (n_out = 8, see dfhm_mlp_decode) in one call:
+ * the network on x_dev[batch][n_in] (BF16), then per sample the fluxes
+ * flux_dev[b][2] (heat W/m2, vapour kg/(m2 s)) and the predicted error of
+ * the sample relative to the wall's RMS flux, err_est_dev[b] = max over the
+ * two fields of sd(u_f) + |u_f| sd(l_f): a sample whose estimate exceeds the
+ * caller's threshold goes back to the DF solver.  scale as for
+ * dfhm_mlp_decode.  Device pointers, queued on the network's stream.
+ * DFHM_E_INVAL for a null pointer, a bad scale or batch outside
+ * [1, max_batch]; DFHM_E_STATE when n_out != 8. */
+dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, const float *scale,
+                           float *flux_dev, float *err_est_dev);
+
 /* Checkpoint / restart.  dfhm_save writes the evolving state of a context —
  * its step index, both levels of every wall in the storage format (FP64
  * values, or the FP32 deviations), the flux state (applied fluxes, Neumaier
  * sums and compensations) and the zone air — into a host buffer after a
  * header (magic, version, precision, wall / node / zone counts and a digest of
- * the wall and zone descriptors).  With buf == NULL it only stores the
+ * everything else the run's future depends on: the run constants -- dt above
+ * all, since levels n and n-1 are one dt apart in the recurrence -- the
+ * material law and start-up mode, every input field of the wall descriptors,
+ * the zone descriptors with their schedules and the zone links).  With buf ==
+ * NULL it only stores the
  * required size in *bytes; otherwise *bytes must hold at least that size
  * (DFHM_E_INVAL) and receives the size written.  dfhm_load restores such a
- * buffer into a context created from the same walls, zones and precision
- * (DFHM_E_INVAL otherwise, state unchanged), which then continues exactly as
+ * buffer into a context created from the same configuration, walls, zones
+ * and links (DFHM_E_INVAL otherwise, state unchanged), which then continues exactly as
  * the saving context would have: the DF recurrence only needs levels n and
  * n-1 (eq. dufort), and the ambient and zone schedules are functions of the
  * step index.  Both synchronise the context's stream; the caller owns buf. */

@@ -13,9 +13,7 @@ With ``bf=True`` the values the GPU stores in BF16 are rounded to BF16
 (round to nearest even) at the same points -- the input, the weights, each
 hidden activation (GELU of the unrounded pre-activation), the pre-activation
 kept for the backward pass, the output-layer gradient and each
-backpropagated gradient -- while every sum is exact FP64.  With
-``pairs=True`` a hidden activation g enters the next layer as the BF16 pair
-hi + lo, hi = bf16(g), lo = bf16(g - hi); the weight gradients use hi.  Parameters use the
+backpropagated gradient -- while every sum is exact FP64.  Parameters use the
 logical order of the ABI: per layer W[n_out][n_in] row-major, then b.
 """
 from __future__ import annotations
@@ -61,7 +59,7 @@ def gelu_d(z):
     return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2 * math.pi)
 
 
-def forward(theta, x, dims, bf=False, pairs=False):
+def forward(theta, x, dims, bf=False):
     """Returns (output [B, n_out], cache)."""
     r = bf16 if bf else (lambda v: np.asarray(v, np.float64))
     layers = unpack(np.asarray(theta, np.float64), *dims)
@@ -73,18 +71,17 @@ def forward(theta, x, dims, bf=False, pairs=False):
         if l < len(layers) - 1:
             pres.append(r(z))
             g = gelu(z)
-            hi = r(g)
-            acts.append(hi)
-            a = hi + r(g - hi) if (bf and pairs) else hi
+            a = r(g)
+            acts.append(a)
         else:
             out = z
     return out, (acts, pres, layers)
 
 
-def loss_and_grad(theta, x, y, dims, bf=False, pairs=False):
+def loss_and_grad(theta, x, y, dims, bf=False):
     """Loss and analytic gradient (logical order)."""
     r = bf16 if bf else (lambda v: np.asarray(v, np.float64))
-    out, (acts, pres, layers) = forward(theta, x, dims, bf, pairs)
+    out, (acts, pres, layers) = forward(theta, x, dims, bf)
     B, F = x.shape[0], out.shape[1] // 2
     mu, s = out[:, :F], out[:, F:2 * F]
     res = y - mu

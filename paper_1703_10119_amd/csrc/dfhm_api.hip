@@ -70,6 +70,8 @@ struct dfhm_ctx {
     double *d_inz = nullptr;          // per zone: heat, vapour gained (streaming)
     int64_t n_links = 0;
     std::vector<RoomDev> rooms_host;
+    std::vector<double> sched_go, sched_qh;            // zone schedules (host copies)
+    std::vector<ZoneLinkDev> links_host;               // per receiving zone, as on the device
     std::vector<std::vector<int32_t>> zone_partners;   // linked zones of each zone
     std::vector<double> zone_mass, zone_cma, zone_sT, zone_sM;   // stability sums
     // captured chunk of streaming steps
@@ -936,6 +938,8 @@ dfhm_status dfhm_room_couple(dfhm_ctx *c, const dfhm_room *rooms, int64_t n_room
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->nr = n_rooms;
     c->rooms_host = rd;
+    c->sched_go = go;
+    c->sched_qh = qh;
     c->zone_partners.assign(n_rooms, {});
     c->packed = false;   // the resident packing must keep zones whole
     return DFHM_OK;
@@ -995,6 +999,7 @@ dfhm_status dfhm_zone_links(dfhm_ctx *c, const dfhm_zone_link *links, int64_t n_
     HIP_TRY(c, hipMemcpyAsync(c->d_rooms, rd.data(), sizeof(RoomDev) * c->nr, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->rooms_host = rd;
+    c->links_host = flat;
     c->n_links = n_links;
     c->extended = true;
     c->packed = false;   // linked zones share a workgroup
@@ -1322,7 +1327,10 @@ struct CkptHeader {
     uint64_t payload;                // bytes after the header
 };
 
-// FNV-1a over the walls' and zones' defining fields (host copies)
+// FNV-1a over everything a run's future depends on besides its evolving
+// state: the run constants (dt above all: levels n and n-1 of the three-level
+// recurrence are one dt apart), the law, every input field of the wall
+// descriptors, the zone descriptors with their schedules, and the links.
 uint64_t describe(const dfhm_ctx *c)
 {
     uint64_t h = 1469598103934665603ull;
@@ -1330,20 +1338,49 @@ uint64_t describe(const dfhm_ctx *c)
         const unsigned char *b = (const unsigned char *)p;
         for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
     };
+    const RunConst &rc = c->rc;
+    for (double v : {rc.dt, rc.Lv, rc.cw, rc.rho_a, rc.c_pa, rc.c_pv, rc.Pv_ref}) mix(&v, sizeof v);
+    mix(&c->cfg.law, sizeof c->cfg.law);
+    mix(&c->cfg.startup, sizeof c->cfg.startup);
     for (const WallDev &W : c->walls) {
         mix(&W.nx, sizeof W.nx);
         mix(&W.n_layers, sizeof W.n_layers);
-        mix(W.lay, sizeof W.lay);
-        mix(W.hT, sizeof W.hT);
-        mix(W.hM, sizeof W.hM);
+        mix(&W.room, sizeof W.room);
+        mix(&W.room_side, sizeof W.room_side);
+        mix(&W.area, sizeof W.area);
         mix(&W.T0, sizeof W.T0);
         mix(&W.RH0, sizeof W.RH0);
+        mix(W.hT, sizeof W.hT);
+        mix(W.hM, sizeof W.hM);
+        mix(W.qinf, sizeof W.qinf);
+        mix(W.ginf, sizeof W.ginf);
+        mix(W.Tamb, sizeof W.Tamb);
+        mix(W.RHamb, sizeof W.RHamb);
+        mix(W.lay, sizeof W.lay);
+        mix(W.qsun, sizeof W.qsun);
+        mix(W.emis, sizeof W.emis);
+        mix(&W.esig, sizeof W.esig);
     }
     mix(c->wall_room.data(), sizeof(int64_t) * c->wall_room.size());
     mix(&c->nr, sizeof c->nr);
-    if (c->cfg.law != DFHM_LAW_SHAPE) mix(&c->cfg.law, sizeof c->cfg.law);
-    for (const auto &p : c->zone_partners)       // linked zones (none: nothing mixed)
-        if (!p.empty()) mix(p.data(), sizeof(int32_t) * p.size());
+    for (const RoomDev &R : c->rooms_host) {
+        mix(&R.volume, sizeof R.volume);
+        mix(&R.ach, sizeof R.ach);
+        mix(&R.T0, sizeof R.T0);
+        mix(&R.RH0, sizeof R.RH0);
+        mix(R.Tout, sizeof R.Tout);
+        mix(R.RHout, sizeof R.RHout);
+        mix(&R.sched_dt, sizeof R.sched_dt);
+        mix(&R.n_sched, sizeof R.n_sched);
+        mix(&R.view, sizeof R.view);
+    }
+    if (!c->sched_go.empty()) mix(c->sched_go.data(), sizeof(double) * c->sched_go.size());
+    if (!c->sched_qh.empty()) mix(c->sched_qh.data(), sizeof(double) * c->sched_qh.size());
+    mix(&c->n_links, sizeof c->n_links);
+    for (const ZoneLinkDev &L : c->links_host) {
+        mix(&L.partner, sizeof L.partner);
+        mix(&L.g, sizeof L.g);
+    }
     return h;
 }
 
@@ -1361,7 +1398,7 @@ dfhm_status dfhm_save(dfhm_ctx *c, void *buf, size_t *bytes)
     if (*bytes < need) return fail(c, DFHM_E_INVAL, "checkpoint buffer too small");
     CkptHeader h{};
     h.magic = kCkptMagic;
-    h.version = 1;
+    h.version = 2;
     h.precision = c->precision;
     h.n_walls = c->nw;
     h.n_nodes = c->N;
@@ -1398,7 +1435,7 @@ dfhm_status dfhm_load(dfhm_ctx *c, const void *buf, size_t bytes)
     CkptHeader h;
     if (bytes < sizeof h) return fail(c, DFHM_E_INVAL, "checkpoint too short");
     std::memcpy(&h, buf, sizeof h);
-    if (h.magic != kCkptMagic || h.version != 1) return fail(c, DFHM_E_INVAL, "not a dfhm checkpoint");
+    if (h.magic != kCkptMagic || h.version != 2) return fail(c, DFHM_E_INVAL, "not a dfhm checkpoint");
     if (h.precision != c->precision || h.n_walls != c->nw || h.n_nodes != c->N || h.n_rooms != c->nr ||
         h.digest != describe(c) || h.payload != ckpt_payload(c) || bytes < sizeof h + h.payload)
         return fail(c, DFHM_E_INVAL, "checkpoint of different walls, zones or precision");
@@ -1536,8 +1573,11 @@ std::string tune_key(const dfhm_ctx *c)
     int64_t nb = 1;
     while (nb < c->N) nb <<= 1;   // size bucket: next power of two of the node count
     char b[256];
-    snprintf(b, sizeof b, "%s p%d s%d g%d n%lld r%lld", arch.c_str(), c->precision, c->cfg.schedule,
-             max_group(c), (long long)nb, (long long)(c->nr > 0));
+    // kernel variant: walls only, zones, or the extended variant (radiative
+    // sources, linked zones); the law changes the node work about twofold
+    const int mode = c->extended ? 2 : (c->nr > 0 ? 1 : 0);
+    snprintf(b, sizeof b, "%s p%d s%d g%d n%lld m%d L%d", arch.c_str(), c->precision, c->cfg.schedule,
+             max_group(c), (long long)nb, mode, (int)c->cfg.law);
     for (char *q = b; *q; ++q)
         if (*q == ' ' || *q == ':') *q = '_';
     return b;

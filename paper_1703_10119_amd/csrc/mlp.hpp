@@ -43,10 +43,9 @@ enum { OP_K = 0, OP_MN = 1 };
 enum {
     EPI_F32 = 0,        // Cf[z][m][n] = acc (split-K partials when gridDim.z > 1)
     EPI_BIAS_F32 = 1,   // Cf[m][n] = acc + bias[n]
-    EPI_BIAS_GELU = 2,  // z = acc + bias[n]: pre[m][n] = bf16(z), Cb[m][n] = bf16(gelu(z))
-    EPI_GELU_BWD = 3,   // Cb[m][n] = bf16(acc * gelu'(aux[m][n]))
-    EPI_BIAS_GELU2 = 4  // as EPI_BIAS_GELU, storing gelu(z) as a BF16 pair:
-                        // Cb[m][n] = hi = bf16(g), Cb[m][N + n] = bf16(g - hi)
+    EPI_BIAS_GELU = 2,  // z = acc + bias[n]: Cb[m][n] = bf16(gelu(z)) and, when pre
+                        // is not null, pre[m][n] = bf16(z) (kept for the backward pass)
+    EPI_GELU_BWD = 3    // Cb[m][n] = bf16(acc * gelu'(aux[m][n]))
 };
 
 constexpr int GB_M = 128, GB_N = 128, GB_K = 32, G_PAD = 8;
@@ -184,13 +183,10 @@ k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
                     Cf[(int64_t)blockIdx.z * M * ldc + o] = v;
                 } else if (EPI == EPI_BIAS_F32) {
                     Cf[o] = v + bias[col];
-                } else if (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS_GELU2) {
+                } else if (EPI == EPI_BIAS_GELU) {
                     const float z = v + bias[col];
-                    const float g = gelu(z);
-                    const uint16_t hi = f2bf(g);
-                    pre[(int64_t)row * N + col] = f2bf(z);
-                    Cb[o] = hi;
-                    if (EPI == EPI_BIAS_GELU2) Cb[o + N] = f2bf(g - bf2f(hi));
+                    if (pre) pre[(int64_t)row * N + col] = f2bf(z);
+                    Cb[o] = f2bf(gelu(z));
                 } else {
                     Cb[o] = f2bf(v * gelu_d(bf2f(aux[o])));
                 }
@@ -352,38 +348,44 @@ __global__ void k_features(const int32_t *__restrict__ wall_of, const double *__
 // e_f = sd(u_f) + |u_f| sd(l_f) to first order, sd = std * exp(s / 2);
 // fallback when e_f > tau for either field.  scale[8] = (mean, std) of
 // u_q, u_g, l_q, l_g.  With several networks (an ensemble trained on the
-// same targets), flux_f and e_f are the means over the members.
+// same targets), flux_f and e_f are the means over the members.  Outputs
+// (each optional): flux[b][2], err[b] = max_f e_f, fallback[b].  A member's
+// outputs of sample b start at y[k] + ld * b.
 struct DecodeScale { float m[4], s[4]; };
 constexpr int kMaxEnsemble = 4;
 struct DecodeNets {
     const float *y[kMaxEnsemble];
-    int n;
+    int n, ld;
 };
 
 __global__ void k_decode(DecodeNets nets, int64_t batch, DecodeScale sc, float tau,
-                         float *__restrict__ flux, uint8_t *__restrict__ fallback)
+                         float *__restrict__ flux, float *__restrict__ err,
+                         uint8_t *__restrict__ fallback)
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     const float inv = 1.0f / (float)nets.n;
+    float emax = 0.f;
     bool fb = false;
     for (int f = 0; f < 2; ++f) {
         float fl = 0.f, e = 0.f;
 #pragma unroll
         for (int k = 0; k < kMaxEnsemble; ++k) {
             if (k < nets.n) {
-                const float *o = nets.y[k] + 8 * b;
+                const float *o = nets.y[k] + (int64_t)nets.ld * b;
                 const float u = o[f] * sc.s[f] + sc.m[f];
                 const float lg = o[2 + f] * sc.s[2 + f] + sc.m[2 + f];
                 fl += u * __expf(lg);
                 e += sc.s[f] * __expf(0.5f * o[4 + f]) + fabsf(u) * sc.s[2 + f] * __expf(0.5f * o[6 + f]);
             }
         }
-        flux[2 * b + f] = fl * inv;
+        if (flux) flux[2 * b + f] = fl * inv;
         e *= inv;
         fb = fb || !(e <= tau);
+        emax = (f == 0 || !(e <= emax)) ? e : emax;   // a NaN estimate propagates
     }
-    fallback[b] = (uint8_t)fb;
+    if (err) err[b] = emax;
+    if (fallback) fallback[b] = (uint8_t)fb;
 }
 
 } // namespace dfhm

@@ -20,10 +20,10 @@ constexpr int kOutPad = 32;   // output layer rows padded for the GEMM tiles
 
 struct Layer {
     int K, N, Np;             // inputs, logical outputs, padded outputs
-    int Kx;                   // reduction length of the forward GEMM: 2K for a BF16-pair input
     size_t w_off, b_off;      // offsets into the flat FP32 parameter buffer
-    size_t wb_off;            // offset of the BF16 weight operand [Np][Kx]
+    size_t wb_off;            // offset of the BF16 weight operand [Np][K]
 };
+
 } // namespace
 
 struct dfhm_mlp {
@@ -33,12 +33,10 @@ struct dfhm_mlp {
     int64_t n_params = 0;      // logical parameters (exposed)
     int64_t n_dev = 0;         // device parameters (with padding)
     int64_t n_wb = 0;          // BF16 weight operands
-    bool pairs = false;        // hidden activations as BF16 pairs
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     uint16_t *wb = nullptr;
     uint8_t *mask = nullptr;
-    std::vector<uint16_t *> act;   // act[0] = input (caller's), act[l+1] = output of layer l
-                                   // ([B][N], or [B][2N] = hi | lo with pairs)
+    std::vector<uint16_t *> act;   // act[0] = input (caller's), act[l+1] = output of layer l [B][N]
     std::vector<uint16_t *> pre;   // pre-activations of hidden layers
     std::vector<uint16_t *> dact;  // gradients w.r.t. layer outputs (BF16)
     float *out = nullptr;          // output layer result [B][kOutPad] FP32
@@ -88,25 +86,33 @@ void gemm(dfhm_mlp *m, int M, int N, int K, const uint16_t *A, int lda, const ui
 
 int blocks_of(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
-// Forward pass over `batch` rows; leaves the output layer in m->out.
-void forward(dfhm_mlp *m, const uint16_t *x, int batch)
+// Forward pass over `batch` rows: layer l reads in(l) and writes its GELU
+// output to out(l) (hidden layers; pre-activations to pre(l) when it is not
+// null), the output layer writes y [batch][kOutPad] (FP32).
+template <typename In, typename Out, typename Pre>
+void forward_into(dfhm_mlp *m, int batch, In in, Out out, Pre pre, float *y)
 {
     const int L = (int)m->layers.size();
-    m->act[0] = const_cast<uint16_t *>(x);
     for (int l = 0; l < L; ++l) {
         const Layer &ly = m->layers[l];
         const uint16_t *W = m->wb + ly.wb_off;
         const float *b = m->w + ly.b_off;
-        if (l < L - 1 && m->pairs)
-            gemm<OP_K, OP_K, EPI_BIAS_GELU2>(m, batch, ly.N, ly.Kx, m->act[l], ly.Kx, W, ly.Kx,
-                                             nullptr, m->act[l + 1], 2 * ly.N, b, nullptr, m->pre[l], 1);
-        else if (l < L - 1)
-            gemm<OP_K, OP_K, EPI_BIAS_GELU>(m, batch, ly.N, ly.Kx, m->act[l], ly.Kx, W, ly.Kx, nullptr,
-                                            m->act[l + 1], ly.N, b, nullptr, m->pre[l], 1);
+        if (l < L - 1)
+            gemm<OP_K, OP_K, EPI_BIAS_GELU>(m, batch, ly.N, ly.K, in(l), ly.K, W, ly.K, nullptr,
+                                            out(l), ly.N, b, nullptr, pre(l), 1);
         else
-            gemm<OP_K, OP_K, EPI_BIAS_F32>(m, batch, ly.Np, ly.Kx, m->act[l], ly.Kx, W, ly.Kx, m->out,
+            gemm<OP_K, OP_K, EPI_BIAS_F32>(m, batch, ly.Np, ly.K, in(l), ly.K, W, ly.K, y,
                                            nullptr, ly.Np, b, nullptr, nullptr, 1);
     }
+}
+
+// Forward pass through the network's own buffers (activations and
+// pre-activations kept for the backward pass); output layer in m->out.
+void forward(dfhm_mlp *m, const uint16_t *x, int batch)
+{
+    m->act[0] = const_cast<uint16_t *>(x);
+    forward_into(m, batch, [m](int l) { return (const uint16_t *)m->act[l]; },
+                 [m](int l) { return m->act[l + 1]; }, [m](int l) { return m->pre[l]; }, m->out);
 }
 
 // Backward pass from dact[L-1] (= dL/dz of the output layer, BF16 [B][Np])
@@ -121,7 +127,7 @@ void backward(dfhm_mlp *m, int batch)
         // weight gradient dW[N][K] = dz^T [N][B] . act[l] [B][K] (the hi half of a pair),
         // split over the batch
         int nsplit = std::max(1, std::min(16, batch / 512));
-        gemm<OP_MN, OP_MN, EPI_F32>(m, Nl, ly.K, batch, dz, Nl, m->act[l], ly.Kx, m->part, nullptr,
+        gemm<OP_MN, OP_MN, EPI_F32>(m, Nl, ly.K, batch, dz, Nl, m->act[l], ly.K, m->part, nullptr,
                                     ly.K, nullptr, nullptr, nullptr, nsplit);
         const int64_t nw = (int64_t)Nl * ly.K;
         hipLaunchKernelGGL(k_sum_partials, dim3(blocks_of(nw, 256)), dim3(256), 0, m->stream,
@@ -143,7 +149,7 @@ void backward(dfhm_mlp *m, int batch)
         // input gradient through the previous GELU: dz_{l-1} = (dz . W) * gelu'(pre_{l-1})
         if (l > 0) {
             const uint16_t *W = m->wb + ly.wb_off;
-            gemm<OP_K, OP_MN, EPI_GELU_BWD>(m, batch, ly.K, Nl, dz, Nl, W, ly.Kx, nullptr,
+            gemm<OP_K, OP_MN, EPI_GELU_BWD>(m, batch, ly.K, Nl, dz, Nl, W, ly.K, nullptr,
                                             m->dact[l - 1], ly.K, nullptr, m->pre[l - 1], nullptr, 1);
         }
     }
@@ -195,8 +201,7 @@ void pack_weights(dfhm_mlp *m)
 {
     for (const Layer &ly : m->layers)
         hipLaunchKernelGGL(k_pack_weights, dim3(blocks_of((int64_t)ly.Np * ly.K, 256)), dim3(256), 0,
-                           m->stream, m->w + ly.w_off, m->wb + ly.wb_off, ly.Np, ly.K, ly.Kx,
-                           (int)(ly.Kx != ly.K));
+                           m->stream, m->w + ly.w_off, m->wb + ly.wb_off, ly.Np, ly.K, ly.K, 0);
 }
 
 dfhm_status upload(dfhm_mlp *m, const std::vector<float> &dev)
@@ -218,24 +223,22 @@ dfhm_status dfhm_mlp_create(const dfhm_mlp_config *cfg, dfhm_mlp **out)
     *out = nullptr;
     if (!cfg || cfg->n_in < 8 || cfg->n_in % 8 || cfg->width < 8 || cfg->width % 8 ||
         cfg->depth < 1 || cfg->depth > 16 || cfg->n_out < 1 || cfg->n_out > kOutPad ||
-        cfg->max_batch < 1 || cfg->max_batch > (1 << 22) || cfg->act_pairs < 0 || cfg->act_pairs > 1)
+        cfg->max_batch < 1 || cfg->max_batch > (1 << 22))
         return DFHM_E_INVAL;
     dfhm_mlp *m = new (std::nothrow) dfhm_mlp();
     if (!m) return DFHM_E_NOMEM;
     m->cfg = *cfg;
     m->stream = (hipStream_t)cfg->stream;
-    m->pairs = cfg->act_pairs == 1;
     size_t o = 0, ob = 0;
     int K = cfg->n_in;
     for (int l = 0; l <= cfg->depth; ++l) {
         Layer ly;
         ly.K = K;
-        ly.Kx = (m->pairs && l > 0) ? 2 * K : K;
         ly.N = l < cfg->depth ? cfg->width : cfg->n_out;
         ly.Np = l < cfg->depth ? ly.N : kOutPad;
         ly.w_off = o; o += (size_t)ly.Np * ly.K;
         ly.b_off = o; o += (size_t)ly.Np;
-        ly.wb_off = ob; ob += (size_t)ly.Np * ly.Kx;
+        ly.wb_off = ob; ob += (size_t)ly.Np * ly.K;
         m->n_params += (int64_t)ly.N * ly.K + ly.N;
         m->layers.push_back(ly);
         K = ly.N;
@@ -256,7 +259,7 @@ dfhm_status dfhm_mlp_create(const dfhm_mlp_config *cfg, dfhm_mlp **out)
         const Layer &ly = m->layers[l];
         const int Nl = l == L - 1 ? ly.Np : ly.N;
         if (l < L - 1) {
-            if (dalloc(m, &m->act[l + 1], (size_t)B * ly.N * (m->pairs ? 2 : 1)) ||
+            if (dalloc(m, &m->act[l + 1], (size_t)B * ly.N) ||
                 dalloc(m, &m->pre[l], (size_t)B * ly.N))
                 return bail(DFHM_E_NOMEM);
         }
@@ -383,9 +386,9 @@ dfhm_status dfhm_mlp_features(const int32_t *wall_dev, const double *t_dev, cons
 }
 
 static dfhm_status decode_nets(const DecodeNets &nets, int64_t batch, const float *scale, float tau,
-                               float *flux_dev, uint8_t *fallback_dev, void *stream)
+                               float *flux_dev, float *err_dev, uint8_t *fallback_dev, void *stream)
 {
-    if (!scale || !flux_dev || !fallback_dev || batch < 0 || !(tau > 0.f)) return DFHM_E_INVAL;
+    if (!scale || !flux_dev || batch < 0 || !(tau > 0.f)) return DFHM_E_INVAL;
     for (int k = 0; k < nets.n; ++k)
         if (!nets.y[k]) return DFHM_E_INVAL;
     if (batch == 0) return DFHM_OK;
@@ -396,28 +399,94 @@ static dfhm_status decode_nets(const DecodeNets &nets, int64_t batch, const floa
         if (!std::isfinite(sc.m[i]) || !(sc.s[i] > 0.f) || !std::isfinite(sc.s[i])) return DFHM_E_INVAL;
     }
     hipLaunchKernelGGL(k_decode, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)stream, nets, batch, sc, tau, flux_dev, fallback_dev);
+                       (hipStream_t)stream, nets, batch, sc, tau, flux_dev, err_dev, fallback_dev);
     return hipGetLastError() == hipSuccess ? DFHM_OK : DFHM_E_DEVICE;
 }
 
 dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scale, float tau,
                             float *flux_dev, uint8_t *fallback_dev, void *stream)
 {
+    if (!fallback_dev) return DFHM_E_INVAL;
     DecodeNets nets{};
     nets.y[0] = y_dev;
     nets.n = 1;
-    return decode_nets(nets, batch, scale, tau, flux_dev, fallback_dev, stream);
+    nets.ld = 8;
+    return decode_nets(nets, batch, scale, tau, flux_dev, nullptr, fallback_dev, stream);
 }
 
 dfhm_status dfhm_mlp_decode_ensemble(const float *const *y_dev, int32_t n_nets, int64_t batch,
                                      const float *scale, float tau, float *flux_dev,
                                      uint8_t *fallback_dev, void *stream)
 {
-    if (!y_dev || n_nets < 1 || n_nets > kMaxEnsemble) return DFHM_E_INVAL;
+    if (!y_dev || !fallback_dev || n_nets < 1 || n_nets > kMaxEnsemble) return DFHM_E_INVAL;
     DecodeNets nets{};
     for (int k = 0; k < n_nets; ++k) nets.y[k] = y_dev[k];
     nets.n = n_nets;
-    return decode_nets(nets, batch, scale, tau, flux_dev, fallback_dev, stream);
+    nets.ld = 8;
+    return decode_nets(nets, batch, scale, tau, flux_dev, nullptr, fallback_dev, stream);
+}
+
+// Shared checks of the two inference calls.
+static dfhm_status infer_args(dfhm_mlp *m, const uint16_t *x, int64_t batch, const float *scale,
+                              const float *flux, const float *err)
+{
+    if (!m) return DFHM_E_INVAL;
+    if (!x || !scale || !flux || !err) return mfail(m, DFHM_E_INVAL, "null argument");
+    if (m->cfg.n_out != 8) return mfail(m, DFHM_E_STATE, "inference decodes the 8-output flux head");
+    if (batch < 1) return mfail(m, DFHM_E_INVAL, "batch out of range");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(scale[2 * i]) || !(scale[2 * i + 1] > 0.f) || !std::isfinite(scale[2 * i + 1]))
+            return mfail(m, DFHM_E_INVAL, "bad output scale");
+    return DFHM_OK;
+}
+
+static dfhm_status infer_decode(dfhm_mlp *m, const float *y, int64_t batch, const float *scale,
+                                float *flux, float *err)
+{
+    DecodeNets nets{};
+    nets.y[0] = y;
+    nets.n = 1;
+    nets.ld = kOutPad;
+    dfhm_status st = decode_nets(nets, batch, scale, 1.0f, flux, err, nullptr, m->stream);
+    if (st) return mfail(m, st, "decode launch failed");
+    return DFHM_OK;
+}
+
+dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, const float *scale,
+                           float *flux_dev, float *err_est_dev)
+{
+    dfhm_status st = infer_args(m, x_dev, batch, scale, flux_dev, err_est_dev);
+    if (st) return st;
+    if (batch > m->cfg.max_batch) return mfail(m, DFHM_E_INVAL, "batch above max_batch");
+    forward(m, x_dev, (int)batch);
+    MHIP(m, hipGetLastError());
+    return infer_decode(m, m->out, batch, scale, flux_dev, err_est_dev);
+}
+
+dfhm_status dfhm_mlp_get_intermediate(dfhm_mlp *m, int32_t kind, int32_t layer, int64_t rows,
+                                      uint16_t *host)
+{
+    if (!m) return DFHM_E_INVAL;
+    const int L = (int)m->layers.size();
+    if (!host || rows < 1 || rows > m->cfg.max_batch) return mfail(m, DFHM_E_INVAL, "bad rows or buffer");
+    const uint16_t *src = nullptr;
+    size_t cols = 0;
+    if (kind == DFHM_MLP_ACT && layer >= 0 && layer < L - 1) {
+        src = m->act[layer + 1];
+        cols = (size_t)m->layers[layer].N;
+    } else if (kind == DFHM_MLP_PRE && layer >= 0 && layer < L - 1) {
+        src = m->pre[layer];
+        cols = (size_t)m->layers[layer].N;
+    } else if (kind == DFHM_MLP_DZ && layer >= 0 && layer < L) {
+        src = m->dact[layer];
+        cols = (size_t)(layer == L - 1 ? m->layers[layer].Np : m->layers[layer].N);
+    } else {
+        return mfail(m, DFHM_E_INVAL, "bad kind or layer");
+    }
+    MHIP(m, hipMemcpyAsync(host, src, sizeof(uint16_t) * cols * (size_t)rows, hipMemcpyDeviceToHost,
+                           m->stream));
+    MHIP(m, hipStreamSynchronize(m->stream));
+    return DFHM_OK;
 }
 
 const char *dfhm_mlp_last_error(const dfhm_mlp *m) { return m ? m->err.c_str() : "null network"; }

@@ -88,7 +88,7 @@ class ImplicitConfig(C.Structure):
 class MlpConfig(C.Structure):
     """dfhm_mlp_config"""
     _fields_ = [("n_in", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
-                ("n_out", C.c_int32), ("max_batch", C.c_int32), ("act_pairs", C.c_int32),
+                ("n_out", C.c_int32), ("max_batch", C.c_int32),
                 ("seed", C.c_uint64), ("beta1", C.c_float), ("beta2", C.c_float),
                 ("eps", C.c_float), ("weight_decay", C.c_float), ("stream", C.c_void_p)]
 
@@ -115,7 +115,8 @@ EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_zone_lin
            "dfhm_mlp_create", "dfhm_mlp_param_count", "dfhm_mlp_get_params",
            "dfhm_mlp_set_params", "dfhm_mlp_forward", "dfhm_mlp_gradients",
            "dfhm_mlp_train_step", "dfhm_mlp_last_error", "dfhm_mlp_destroy",
-           "dfhm_mlp_features", "dfhm_mlp_decode", "dfhm_mlp_decode_ensemble")
+           "dfhm_mlp_features", "dfhm_mlp_decode", "dfhm_mlp_decode_ensemble",
+           "dfhm_mlp_get_intermediate", "dfhm_mlp_infer")
 
 _lib = None
 
@@ -189,9 +190,12 @@ def load(path: str = LIB_PATH):
     L.dfhm_mlp_features.argtypes = [P, P, P, P, I64, C.POINTER(FeatureDesc), P, P]
     L.dfhm_mlp_decode.argtypes = [P, I64, P, C.c_float, P, P, P]
     L.dfhm_mlp_decode_ensemble.argtypes = [P, I32, I64, P, C.c_float, P, P, P]
+    L.dfhm_mlp_infer.argtypes = [P, P, I64, P, P, P]
+    L.dfhm_mlp_get_intermediate.argtypes = [P, I32, I32, I64, P]
     for f in (L.dfhm_mlp_create, L.dfhm_mlp_get_params, L.dfhm_mlp_set_params,
               L.dfhm_mlp_forward, L.dfhm_mlp_gradients, L.dfhm_mlp_train_step,
-              L.dfhm_mlp_features, L.dfhm_mlp_decode, L.dfhm_mlp_decode_ensemble):
+              L.dfhm_mlp_features, L.dfhm_mlp_decode, L.dfhm_mlp_decode_ensemble,
+              L.dfhm_mlp_infer, L.dfhm_mlp_get_intermediate):
         f.restype = C.c_int
     _lib = L
     return L

@@ -43,17 +43,16 @@ class MLP:
     """The network on the current device (BF16 MFMA, FP32 master weights)."""
 
     def __init__(self, n_in=STRIDE, width=512, depth=4, n_out=8, max_batch=65536, seed=0,
-                 beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, act_pairs=False):
+                 beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
         L = _lib()
-        c = MlpConfig(n_in, width, depth, n_out, max_batch, int(bool(act_pairs)), seed, beta1,
-                      beta2, eps, weight_decay, _stream())
+        c = MlpConfig(n_in, width, depth, n_out, max_batch, seed, beta1, beta2, eps,
+                      weight_decay, _stream())
         h = C.c_void_p()
         st = L.dfhm_mlp_create(C.byref(c), C.byref(h))
         if st != 0:
             raise dfhm.DfhmError(st, "dfhm_mlp_create")
         self._h = h
         self.dims = (n_in, width, depth, n_out)
-        self.act_pairs = bool(act_pairs)
         self.n_params = int(L.dfhm_mlp_param_count(h))
         self.max_batch = max_batch
 
@@ -78,6 +77,31 @@ class MLP:
         y = torch.empty((B, self.dims[3]), dtype=torch.float32, device=x.device)
         self._check(_lib().dfhm_mlp_forward(self._h, x.data_ptr(), B, y.data_ptr()), "forward")
         return y
+
+    def infer(self, x, scale):
+        """Fluxes [B, 2] and predicted relative errors [B] of the flux head
+        (dfhm_mlp_infer); scale = 8 floats."""
+        import torch
+        B = x.shape[0]
+        flux = torch.empty((B, 2), dtype=torch.float32, device=x.device)
+        err = torch.empty(B, dtype=torch.float32, device=x.device)
+        sc = np.ascontiguousarray(scale, np.float32)
+        self._check(_lib().dfhm_mlp_infer(self._h, x.data_ptr(), B, sc.ctypes.data_as(C.c_void_p), flux.data_ptr(),
+                       err.data_ptr()), "infer")
+        return flux, err
+
+    ACT, PRE, DZ = 0, 1, 2
+
+    def intermediate(self, kind, layer, rows):
+        """BF16 bit patterns (uint16 [rows, cols]) of a stored intermediate of
+        the last pass (dfhm_mlp_get_intermediate)."""
+        n_in, width, depth, n_out = self.dims
+        cols = 32 if (kind == self.DZ and layer == depth) else width
+        out = np.empty((rows, cols), np.uint16)
+        self._check(_lib().dfhm_mlp_get_intermediate(self._h, int(kind), int(layer), int(rows),
+                                                     out.ctypes.data_as(C.c_void_p)),
+                    "get_intermediate")
+        return out
 
     def train_step(self, x, y, lr, want_loss=False):
         loss = C.c_float(0.0)
@@ -295,7 +319,7 @@ def calibrate_tau(nets, walls, data, desc, targets, target=0.01, q=0.99):
 
 
 def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=16384,
-          target=0.01, q=0.99, cal_margin=0.9, seed=1, act_pairs=False, n_nets=3, log=None):
+          target=0.01, q=0.99, cal_margin=0.9, seed=1, n_nets=3, log=None):
     """Train on DF histories, calibrate the fallback threshold on one set of
     walls and measure error and speed-up on another (all C2-type walls:
     30 cm, 1001 nodes, dt = 1 s, different generator seeds).  With n_nets > 1
@@ -323,7 +347,7 @@ def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=1638
     targets = Targets(d_tr["flux"])
     _, params = wall_inputs(tr)
     desc = feature_desc(params, d_tr["t"][0], d_tr["t"][-1])
-    nets = [MLP(max_batch=65536, seed=seed + k, act_pairs=act_pairs) for k in range(n_nets)]
+    nets = [MLP(max_batch=65536, seed=seed + k) for k in range(n_nets)]
     fits = []
     for k, net in enumerate(nets):
         say(f"training network {k + 1} of {n_nets}")
@@ -368,14 +392,14 @@ def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=1638
         epochs=epochs, batch=batch, lr=lr, n_nets=n_nets)
 
 
-def kernel_bench(batch=65536, train_batch=16384, iters=50, act_pairs=False, seed=0):
+def kernel_bench(batch=65536, train_batch=16384, iters=50, seed=0):
     """Time the network's kernels alone on synthetic BF16 inputs: forward at
     the inference batch and one AdamW training step, with HIP events on the
     stream the kernels are launched on.  FLOPs are the GEMMs' multiply-adds
     (2 per weight per sample; x3 for a training step)."""
     import torch
     dev = "cuda"
-    net = MLP(max_batch=max(batch, train_batch), seed=seed, act_pairs=act_pairs)
+    net = MLP(max_batch=max(batch, train_batch), seed=seed)
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
     x = (torch.randn((batch, STRIDE), generator=g, device=dev)
@@ -384,9 +408,7 @@ def kernel_bench(batch=65536, train_batch=16384, iters=50, act_pairs=False, seed
     yt = torch.randn((train_batch, 4), generator=g, device=dev)
     stream = torch.cuda.current_stream()
     n_w = net.n_params - sum(net.dims[1] for _ in range(net.dims[2])) - net.dims[3]
-    mult = 2.0 if act_pairs else 1.0          # pairs double every GEMM after the first
-    k_first = net.dims[0] * net.dims[1]
-    fwd_flops = 2.0 * (k_first + mult * (n_w - k_first))
+    fwd_flops = 2.0 * n_w
 
     def timed(fn, n):
         fn()
@@ -413,6 +435,5 @@ if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser(description="surrogate kernel timing")
     ap.add_argument("--iters", type=int, default=50)
-    ap.add_argument("--pairs", action="store_true")
     a = ap.parse_args()
-    print(json.dumps(kernel_bench(iters=a.iters, act_pairs=a.pairs)), flush=True)
+    print(json.dumps(kernel_bench(iters=a.iters)), flush=True)

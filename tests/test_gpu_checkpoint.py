@@ -94,3 +94,40 @@ def test_checkpoint_of_other_walls_or_precision_is_refused():
     with pytest.raises(dfhm.DfhmError):
         a.load(bytes(bad))
     assert b.n == 0 and c.n == 0
+
+
+def test_checkpoint_of_another_dt_or_zone_is_refused():
+    """The digest covers the run constants and the zone descriptors: a
+    checkpoint written at another dt (levels n and n-1 one old dt apart), or
+    for a zone of another volume, another schedule or without its links, is
+    refused and leaves the context unchanged."""
+    walls, rooms = wl.building_batch(2, seed=46, dt=10.0)
+    cfg = wl.default_config(dt=10.0)
+    a = dfhm.Solver(walls, cfg, rooms=rooms, schedule=dfhm.SCHED_STREAM)
+    a.step(25)
+    ck = a.save()
+    b = dfhm.Solver(walls, wl.default_config(dt=5.0), rooms=rooms, schedule=dfhm.SCHED_STREAM)
+    with pytest.raises(dfhm.DfhmError):
+        b.load(ck)
+    assert b.n == 0
+    r2 = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in rooms.items()}
+    r2["volume"][1] *= 1.01
+    c = dfhm.Solver(walls, cfg, rooms=r2, schedule=dfhm.SCHED_STREAM)
+    with pytest.raises(dfhm.DfhmError):
+        c.load(ck)
+    r3 = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in rooms.items()}
+    r3["g_o"][0, 5] += 1e-6
+    d = dfhm.Solver(walls, cfg, rooms=r3, schedule=dfhm.SCHED_STREAM)
+    with pytest.raises(dfhm.DfhmError):
+        d.load(ck)
+    w2 = {k: v.copy() for k, v in walls.items()}
+    w2["Tamb"][3, 0, 1] += 0.5          # another outdoor amplitude
+    e = dfhm.Solver(w2, cfg, rooms=rooms, schedule=dfhm.SCHED_STREAM)
+    with pytest.raises(dfhm.DfhmError):
+        e.load(ck)
+    # the same setup accepts it
+    f = dfhm.Solver(walls, cfg, rooms=rooms, schedule=dfhm.SCHED_STREAM)
+    f.load(ck)
+    assert f.n == 25
+    for s in (a, b, c, d, e, f):
+        s.close()

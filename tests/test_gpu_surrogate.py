@@ -1,21 +1,29 @@
 """GPU tests of the surface-flux surrogate kernels through the C ABI.
 
 The network is not part of the paper, so its parity is pinned by the CPU
-network oracle (FP64 sums, BF16 rounding emulated at the points where the
-kernels store BF16) and by its own gradient check, not by the paper.
+network oracle (FP64 sums, BF16 rounding at the points where the kernels
+store BF16) and by its own gradient check, not by the paper.
 
-Tolerances.  The kernels accumulate in FP32 and store hidden activations and
-gradients in BF16.  Against the oracle with the same BF16 rounding points,
-the differences come from the summation order and FP32 accumulation
-(relative ~sqrt(K) 2^-24 per dot product).  Now and then that moves a value
-across a BF16 rounding boundary -- a change of one BF16 ulp (2^-8 relative)
-in that element, with probability ~sqrt(K) 2^-24 / 2^-9 ~ 3e-4 per element
-at K = 512 -- and each such flip reaches an output or gradient diluted over
-the fan-in (~2^-8 / sqrt(512) ~ 2e-4 relative per flip), compounding over
-the layers a gradient passes through (up to 2 x depth + 1 BF16 stores).
-Relative L2 errors are bounded by 3e-3 here, and where the batch resolves it
-the error must also stay below 0.3 x the BF16-vs-FP64 difference (the oracle
-without BF16 rounding): the kernels round where the oracle says.
+Element by element, layer by layer.  Each layer is checked given the GPU's
+own inputs to that layer (its stored BF16 activations, pre-activations and
+gradients, read back through dfhm_mlp_get_intermediate), so that every
+element has an exact FP64 value and a rigorous interval for the GPU result:
+  * a K-term dot product of BF16 operands accumulated in FP32 in any order
+    (the products are exact in FP32) is within gamma_K sum |a b| of the exact
+    sum, gamma_K = K 2^-24 / (1 - K 2^-24); one more FP32 rounding per bias
+    add or product;
+  * GELU is 1.13-Lipschitz, and the FP32 GELU (erff) and its derivative are
+    within 1e-6 |z| + 1e-7 of the exact ones;
+  * BF16 rounding (nearest even) is monotone, so a BF16 value computed from
+    anything inside [lo, hi] lies in [bf16(lo), bf16(hi)].
+Every element must lie in its interval: activations, pre-activations,
+outputs, every backpropagated gradient and every weight and bias gradient.
+Across the whole network (no teacher forcing) a value now and then crosses a
+BF16 rounding boundary on one side and not the other, a flip of one BF16 ulp
+that then spreads through the following layers; there the relative L2 error
+must stay below 3e-3 and below 0.3 x the gap between the BF16 and the FP64
+oracle (the kernels round where the oracle says), and the test reports how
+many outputs fall outside their no-flip interval.
 """
 import ctypes as C
 import math
@@ -53,66 +61,199 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _net(dims, batch, seed=3, wd=0.0, pairs=False):
+def _net(dims, batch, seed=3, wd=0.0):
     from paper_1703_10119_amd import surrogate
     n_in, width, depth, n_out = dims
     return surrogate.MLP(n_in=n_in, width=width, depth=depth, n_out=n_out, max_batch=batch,
-                         seed=seed, weight_decay=wd, act_pairs=pairs)
+                         seed=seed, weight_decay=wd)
 
 
 # ragged against the 128 x 128 x 32 tiles in every dimension
 DIMS = [(40, 136, 2, 4), (584, 512, 4, 8), (8, 8, 1, 4)]
 BATCH = [300, 1000, 1]
 
+U32 = 2.0 ** -24
 
-@pytest.mark.parametrize("pairs", [False, True])
+
+def _gamma(k):
+    return k * U32 / (1.0 - k * U32)
+
+
+def _bf(x):
+    return mlp_ref.bf16(x)
+
+
+def _gelu_exact(z):
+    return mlp_ref.gelu(z)
+
+
+def _in_bf16_interval(got, lo, hi):
+    """got (BF16 values as FP64) within [bf16(lo), bf16(hi)], elementwise."""
+    return (got >= _bf(lo)) & (got <= _bf(hi))
+
+
+def _dot_interval(A, B, bias=None):
+    """Exact A @ B (+ bias) in FP64 and the FP32 accumulation bound of each
+    element (products exact, any summation order, one rounding for the bias
+    add; a 2^-53 K term covers the FP64 reference sum itself)."""
+    K = A.shape[1]
+    s = A @ B
+    mag = np.abs(A) @ np.abs(B)
+    if bias is not None:
+        s = s + bias
+    bound = (_gamma(K + 1) + K * 2.0 ** -53) * mag + U32 * np.abs(s) + 1e-30
+    return s, bound
+
+
+def _layers(net, theta):
+    return [(_bf(W), b.astype(np.float32).astype(np.float64))
+            for W, b in mlp_ref.unpack(theta, *net.dims)]
+
+
 @pytest.mark.parametrize("dims,batch", list(zip(DIMS, BATCH)))
-def test_forward_matches_oracle(dims, batch, pairs):
+def test_forward_layer_by_layer(dims, batch):
+    """Every activation, pre-activation and output of the forward pass lies
+    in its interval around the exact value computed from the GPU's own
+    inputs to that layer."""
     dev = _dev()
     rng = np.random.default_rng(11)
     theta = mlp_ref.init(*dims[:3], seed=5, n_out=dims[3])
     theta[-dims[3]:] = rng.normal(0, 0.2, dims[3])
-    x = rng.normal(0, 1, (batch, dims[0]))
-    xb = _bf16_bits(x)
-    net = _net(dims, batch, pairs=pairs)
+    xb = _bf16_bits(rng.normal(0, 1, (batch, dims[0])))
+    net = _net(dims, batch)
     net.set_params(theta)
     y = net.forward(torch.tensor(xb, device=dev)).cpu().numpy().astype(np.float64)
-    ref, _ = mlp_ref.forward(theta, _bits_to_f(xb), dims, bf=True, pairs=pairs)
-    ref_fp64, _ = mlp_ref.forward(theta, x, dims, bf=False)
+    layers = _layers(net, theta)
+    a = _bits_to_f(xb)
+    n_checked = 0
+    for l, (W, b) in enumerate(layers):
+        s, B = _dot_interval(a, W.T, b)
+        if l < len(layers) - 1:
+            pre = _bits_to_f(net.intermediate(net.PRE, l, batch))
+            act = _bits_to_f(net.intermediate(net.ACT, l, batch))
+            ok_pre = _in_bf16_interval(pre, s - B, s + B)
+            g = _gelu_exact(s)
+            slack = 1.13 * B + 1e-6 * np.abs(s) + 1e-7
+            ok_act = _in_bf16_interval(act, g - slack, g + slack)
+            print(f"layer {l}: {ok_pre.size} pre-activations, {ok_act.size} activations; "
+                  f"outside: {np.count_nonzero(~ok_pre)}, {np.count_nonzero(~ok_act)}")
+            assert ok_pre.all() and ok_act.all(), (l, np.argwhere(~ok_pre)[:5], np.argwhere(~ok_act)[:5])
+            n_checked += ok_pre.size + ok_act.size
+            a = act
+        else:
+            err = np.abs(y - s)
+            print(f"output: max |y - exact| / bound = {np.max(err / B):.3f}")
+            assert np.all(err <= B)
+            n_checked += y.size
+    assert n_checked > 0
+    # whole network against the BF16 oracle (flips spread; norm bars)
+    ref, (ref_acts, _, _) = mlp_ref.forward(theta, _bits_to_f(xb), dims, bf=True)
+    ref_fp64, _ = mlp_ref.forward(theta, _bits_to_f(xb), dims, bf=False)
     e = _rel(y, ref)
-    print(f"forward dims={dims} batch={batch} pairs={pairs}: rel L2 vs bf16 oracle {e:.2e}, "
-          f"bf16 oracle vs fp64 {_rel(ref, ref_fp64):.2e}")
+    _, Bref = _dot_interval(ref_acts[-1], layers[-1][0].T, layers[-1][1])
+    n_out = int(np.count_nonzero(np.abs(y - ref) > Bref))
+    print(f"forward dims={dims} batch={batch}: rel L2 vs bf16 oracle {e:.2e}, "
+          f"bf16 oracle vs fp64 {_rel(ref, ref_fp64):.2e}; {n_out} of {y.size} outputs "
+          f"outside the no-flip interval (BF16 flips upstream)")
     assert e <= 3e-3
     if batch >= 100:
         assert e < 0.2 * _rel(ref, ref_fp64)
     net.close()
 
 
-@pytest.mark.parametrize("pairs", [False, True])
+def _loss_dz_interval(yg, yt, F, B):
+    """Interval of the BF16 loss gradient dz of the output layer (k_loss)
+    from the GPU's FP32 outputs yg [B, >= 2F] and the FP32 targets yt."""
+    mu, s = yg[:, :F], yg[:, F:2 * F]
+    r = yt - mu                                   # exact in FP64
+    e = np.exp(-s)
+    v_mean = -2.0 * r / B
+    d_mean = 4 * U32 * np.abs(v_mean) + 1e-30
+    v_var = (1.0 - r * r * e) / B
+    d_var = (2e-6 * r * r * e + 4 * U32 * (1.0 + r * r * e)) / B + 1e-30
+    lo = np.concatenate([v_mean - d_mean, v_var - d_var], 1)
+    hi = np.concatenate([v_mean + d_mean, v_var + d_var], 1)
+    return lo, hi
+
+
 @pytest.mark.parametrize("dims,batch", list(zip(DIMS, BATCH)))
-def test_gradients_match_oracle(dims, batch, pairs):
+def test_gradients_layer_by_layer(dims, batch):
+    """Every backpropagated gradient and every weight and bias gradient lies
+    in its interval around the exact value computed from the GPU's own
+    stored inputs to that step; the loss and the whole gradient also stay
+    close to the BF16 oracle's."""
     dev = _dev()
     rng = np.random.default_rng(12)
     F = dims[3] // 2
     theta = mlp_ref.init(*dims[:3], seed=6, n_out=dims[3])
     theta[-dims[3]:] = rng.normal(0, 0.2, dims[3])
     x = rng.normal(0, 1, (batch, dims[0]))
-    y = rng.normal(0, 1, (batch, F))
+    yt = rng.normal(0, 1, (batch, F)).astype(np.float32).astype(np.float64)
     xb = _bf16_bits(x)
-    net = _net(dims, batch, pairs=pairs)
+    net = _net(dims, batch)
     net.set_params(theta)
-    g, loss = net.gradients(torch.tensor(xb, device=dev),
-                            torch.tensor(y, dtype=torch.float32, device=dev))
-    y32 = y.astype(np.float32).astype(np.float64)
-    rl, rg = mlp_ref.loss_and_grad(theta, _bits_to_f(xb), y32, dims, bf=True, pairs=pairs)
-    _, rg64 = mlp_ref.loss_and_grad(theta, x, y32, dims, bf=False)
-    # the loss moves with the outputs (rel L2 <= 3e-3 above): 1e-3 relative
+    xd = torch.tensor(xb, device=dev)
+    g, loss = net.gradients(xd, torch.tensor(yt, dtype=torch.float32, device=dev))
+    g = g.astype(np.float64)
+    layers = _layers(net, theta)
+    L = len(layers)
+    depth = dims[2]
+    # the forward pass of this call: stored activations and pre-activations
+    acts = [_bits_to_f(xb)] + [_bits_to_f(net.intermediate(net.ACT, l, batch)) for l in range(depth)]
+    pres = [_bits_to_f(net.intermediate(net.PRE, l, batch)) for l in range(depth)]
+    yg = np.asarray(net.forward(xd).cpu().numpy(), np.float64)   # same inputs: same outputs
+    # output-layer gradient: from the GPU's outputs by the loss definition
+    dz_lo, dz_hi = _loss_dz_interval(yg, yt, F, batch)
+    dzL = _bits_to_f(net.intermediate(net.DZ, depth, batch))[:, :dims[3]]
+    ok = _in_bf16_interval(dzL[:, :F], dz_lo[:, :F], dz_hi[:, :F])
+    assert ok.all()
+    assert np.all(dzL[:, F:] == 0.0)            # log variances: output layer only
+    offs = np.cumsum([0] + [n * k + n for n, k in mlp_ref.shapes(*dims[:3], n_out=dims[3])])
+    for l in range(L - 1, -1, -1):
+        W, _ = layers[l]
+        n_out, k_in = W.shape
+        gW = g[offs[l]:offs[l] + n_out * k_in].reshape(n_out, k_in)
+        gb = g[offs[l] + n_out * k_in:offs[l + 1]]
+        a = acts[l]
+        if l == L - 1:
+            # the log-variance columns were zeroed after this layer's own
+            # gradients: take them as intervals from the loss definition
+            lo = np.concatenate([dzL[:, :F], _bf(dz_lo[:, F:])], 1)
+            hi = np.concatenate([dzL[:, :F], _bf(dz_hi[:, F:])], 1)
+        else:
+            lo = hi = _bits_to_f(net.intermediate(net.DZ, l, batch))
+        # weight gradient dz^T a: interval sum over the batch + FP32 accumulation
+        ap, an = np.maximum(a, 0.0), np.minimum(a, 0.0)
+        p_lo = lo.T @ ap + hi.T @ an
+        p_hi = hi.T @ ap + lo.T @ an
+        mag = (np.maximum(np.abs(lo), np.abs(hi)).T @ np.abs(a))
+        Bw = (_gamma(batch + 16) + batch * 2.0 ** -53) * mag + 1e-30
+        okW = (gW >= p_lo - Bw) & (gW <= p_hi + Bw)
+        Bb = (_gamma(batch + 64) + batch * 2.0 ** -53) * np.maximum(np.abs(lo), np.abs(hi)).sum(0) + 1e-30
+        okb = (gb >= lo.sum(0) - Bb) & (gb <= hi.sum(0) + Bb)
+        print(f"layer {l}: {gW.size} weight and {gb.size} bias gradients, outside "
+              f"{np.count_nonzero(~okW)} / {np.count_nonzero(~okb)}")
+        assert okW.all() and okb.all(), (l, np.argwhere(~okW)[:5], np.argwhere(~okb)[:5])
+        if l > 0:
+            # backpropagated gradient into the previous GELU
+            dz = _bits_to_f(net.intermediate(net.DZ, l, batch))[:, :n_out]
+            s, Bs = _dot_interval(dz, W)
+            z = pres[l - 1]
+            gd = mlp_ref.gelu_d(z)
+            v = s * gd
+            slack = Bs * np.abs(gd) + (np.abs(s) + Bs) * (1e-6 * np.abs(z) + 1e-7) + U32 * np.abs(v)
+            got = _bits_to_f(net.intermediate(net.DZ, l - 1, batch))
+            okd = _in_bf16_interval(got, v - slack, v + slack)
+            print(f"  dz into layer {l - 1}: {okd.size}, outside {np.count_nonzero(~okd)}")
+            assert okd.all(), (l, np.argwhere(~okd)[:5])
+    # whole network against the BF16 oracle
+    rl, rg = mlp_ref.loss_and_grad(theta, _bits_to_f(xb), yt, dims, bf=True)
+    _, rg64 = mlp_ref.loss_and_grad(theta, _bits_to_f(xb), yt, dims, bf=False)
     assert abs(loss - rl) <= 1e-3 * max(1.0, abs(rl))
-    # per layer (weights and biases separately)
     o = 0
     for n, k in mlp_ref.shapes(*dims[:3], n_out=dims[3]):
         for size in (n * k, n):
-            e = _rel(g[o:o + size].astype(np.float64), rg[o:o + size])
+            e = _rel(g[o:o + size], rg[o:o + size])
             gap = _rel(rg[o:o + size], rg64[o:o + size])
             print(f"grad block @{o} size {size}: rel L2 {e:.2e} (bf16 vs fp64 {gap:.2e})")
             assert e <= 3e-3, (o, size, e)
@@ -121,6 +262,50 @@ def test_gradients_match_oracle(dims, batch, pairs):
             o += size
     assert o == g.size
     net.close()
+
+
+def test_infer_matches_forward_and_decode():
+    """dfhm_mlp_infer = the network's forward pass followed by the flux
+    decode: the same fluxes as dfhm_mlp_forward + dfhm_mlp_decode bit for bit,
+    and the predicted error max_f sd(u_f) + |u_f| sd(l_f) by its definition
+    from the forward outputs."""
+    dev = _dev()
+    rng = np.random.default_rng(18)
+    dims, batch = (584, 512, 4, 8), 3001
+    theta = mlp_ref.init(*dims[:3], seed=8, n_out=8)
+    theta[-8:] = rng.normal(0, 0.2, 8)
+    theta[-4:] -= 8.0                        # log variances around -8
+    net = _net(dims, batch)
+    net.set_params(theta)
+    x = torch.tensor(_bf16_bits(rng.normal(0, 1, (batch, dims[0]))), device=dev)
+    scale = np.array([0.1, 1.2, -0.3, 0.9, 1.0, 0.5, -14.0, 0.8], np.float32)
+    flux, err = net.infer(x, scale)
+    y = net.forward(x)
+    f2 = torch.empty((batch, 2), dtype=torch.float32, device=dev)
+    fb = torch.empty(batch, dtype=torch.uint8, device=dev)
+    st = dfhm.load().dfhm_mlp_decode(y.data_ptr(), batch, scale.ctypes.data_as(C.c_void_p), 0.01,
+                                     f2.data_ptr(), fb.data_ptr(),
+                                     torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.equal(flux, f2)
+    yv = y.cpu().numpy().astype(np.float64)
+    m, sd = scale[0::2].astype(np.float64), scale[1::2].astype(np.float64)
+    u = yv[:, :2] * sd[:2] + m[:2]
+    e = (sd[:2] * np.exp(0.5 * yv[:, 4:6]) + np.abs(u) * sd[2:] * np.exp(0.5 * yv[:, 6:8])).max(1)
+    got = err.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - e) <= 1e-5 * e + 1e-6 * np.abs(m[:2]).max() * sd[2:].max())
+    assert np.array_equal(fb.cpu().numpy().astype(bool), got > 0.01)
+    # argument errors
+    bad = scale.copy()
+    bad[3] = -1.0
+    with pytest.raises(dfhm.DfhmError):
+        net.infer(x, bad)
+    net.close()
+    net4 = _net((40, 136, 2, 4), 16)
+    with pytest.raises(dfhm.DfhmError):
+        net4.infer(torch.zeros((16, 40), dtype=torch.int16, device=dev), scale)   # n_out != 8
+    net4.close()
 
 
 def test_adamw_first_step():
@@ -313,7 +498,7 @@ def test_mlp_argument_errors():
     for bad in [dict(n_in=12), dict(width=0), dict(depth=17), dict(n_out=33), dict(max_batch=0)]:
         kw = dict(n_in=16, width=16, depth=1, n_out=4, max_batch=8)
         kw.update(bad)
-        c = dfhm.MlpConfig(kw["n_in"], kw["width"], kw["depth"], kw["n_out"], kw["max_batch"], 0,
+        c = dfhm.MlpConfig(kw["n_in"], kw["width"], kw["depth"], kw["n_out"], kw["max_batch"],
                            0, 0.9, 0.999, 1e-8, 0.0, None)
         assert L.dfhm_mlp_create(C.byref(c), C.byref(h)) == 1, bad     # DFHM_E_INVAL
     net = S.MLP(n_in=16, width=16, depth=1, n_out=4, max_batch=8)

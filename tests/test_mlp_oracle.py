@@ -94,31 +94,6 @@ def test_bf16_rounding():
     assert np.isfinite(out[6])
 
 
-def test_bf16_pairs_approach_fp64():
-    """Activations carried as BF16 pairs (16 significant bits) bring the BF16
-    forward pass an order of magnitude closer to the FP64 one, and the pair
-    itself represents a value to within 2^-16 relative."""
-    rng = np.random.default_rng(5)
-    dims = (32, 64, 4, 8)
-    theta = mlp_ref.init(32, 64, 4, seed=6, n_out=8)
-    x = mlp_ref.bf16(rng.normal(0, 1, (200, 32)))
-    y64, _ = mlp_ref.forward(theta, x, dims)
-    y1, _ = mlp_ref.forward(theta, x, dims, bf=True)
-    y2, _ = mlp_ref.forward(theta, x, dims, bf=True, pairs=True)
-    # weights stay BF16 in both, so compare against FP64 with BF16 weights
-    tq = np.concatenate([np.concatenate([mlp_ref.bf16(W).ravel(), b])
-                         for W, b in mlp_ref.unpack(theta, *dims)])
-    yq, _ = mlp_ref.forward(tq, x, dims)
-    e1 = np.linalg.norm(y1 - yq) / np.linalg.norm(yq)
-    e2 = np.linalg.norm(y2 - yq) / np.linalg.norm(yq)
-    assert e2 < e1 / 30, (e1, e2)
-    assert np.linalg.norm(y1 - y64) > 0
-    g = rng.normal(0, 1, 1000)
-    hi = mlp_ref.bf16(g)
-    lo = mlp_ref.bf16(g - hi)
-    assert np.all(np.abs(hi + lo - g) <= 2.0 ** -16 * np.abs(g))
-
-
 # GELU(z) = z Phi(z) with the standard normal CDF Phi, and its derivative
 # Phi(z) + z phi(z): Phi(1) = 0.8413447460685429, phi(1) = 0.24197072451914337
 # (textbook values of the normal distribution).
