@@ -415,6 +415,20 @@ dfhm_status dfhm_mlp_decode_ensemble(const float *const *y_dev, int32_t n_nets, 
 dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, const float *scale,
                            float *flux_dev, float *err_est_dev);
 
+/* dfhm_mlp_infer for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops): the same results, with the hidden
+ * activations and the raw outputs in one statically allocated 64 MiB device
+ * array per GPU instead of the network's buffers; it calls no allocator.
+ * batch may not exceed dfhm_mlp_noalloc_max_batch(m) (30,840 rows at width
+ * 512; DFHM_E_INVAL above it).  Calls on one GPU share that array: two calls
+ * whose work overlaps on one GPU (different streams, or threads) race, and
+ * the caller must order them.  Errors as dfhm_mlp_infer, and DFHM_E_DEVICE
+ * if the array's address could not be resolved when the network was
+ * created. */
+dfhm_status dfhm_mlp_infer_noalloc(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch,
+                                   const float *scale, float *flux_dev, float *err_est_dev);
+int64_t dfhm_mlp_noalloc_max_batch(const dfhm_mlp *m);
+
 /* Checkpoint / restart.  dfhm_save writes the evolving state of a context —
  * its step index, both levels of every wall in the storage format (FP64
  * values, or the FP32 deviations), the flux state (applied fluxes, Neumaier

@@ -1,11 +1,13 @@
 // mlp_api.hip -- host side of the surface-flux surrogate (dfhm_mlp_* in
 // include/dfhm.h).  Device memory: FP32 master weights, BF16 copies, AdamW
 // moments, gradients, activations (BF16) and pre-activations (BF16) of every
-// layer for the largest batch, split-K partials.
+// layer for the largest batch, split-K partials; and one file-scope device
+// array, the scratch of the allocation-free inference call.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -24,6 +26,35 @@ struct Layer {
     size_t wb_off;            // offset of the BF16 weight operand [Np][K]
 };
 
+// Scratch of dfhm_mlp_infer_noalloc: two hidden-activation buffers used in
+// turn and the padded output layer, for at most kScratchBytes.  Every GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// uses the name `scratch` as an address: its device address is looked up once
+// per device (hipGetSymbolAddress, with that device current) and kept in
+// g_scratch.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device); nullptr
+// and a message on failure.
+void *scratch_on(int dev, std::string &msg)
+{
+    if (dev < 0 || dev >= kMaxDevices) { msg = "device index beyond the scratch table"; return nullptr; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch[dev] = p;
+    }
+    return g_scratch[dev];
+}
 } // namespace
 
 struct dfhm_mlp {
@@ -33,6 +64,9 @@ struct dfhm_mlp {
     int64_t n_params = 0;      // logical parameters (exposed)
     int64_t n_dev = 0;         // device parameters (with padding)
     int64_t n_wb = 0;          // BF16 weight operands
+    int device = 0;            // device the network lives on
+    void *scratch = nullptr;   // that device's address of `scratch` (nullptr: not available)
+    std::string scratch_msg;   // why it is not
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     uint16_t *wb = nullptr;
     uint8_t *mask = nullptr;
@@ -229,6 +263,8 @@ dfhm_status dfhm_mlp_create(const dfhm_mlp_config *cfg, dfhm_mlp **out)
     if (!m) return DFHM_E_NOMEM;
     m->cfg = *cfg;
     m->stream = (hipStream_t)cfg->stream;
+    if (hipGetDevice(&m->device) != hipSuccess) { delete m; return DFHM_E_DEVICE; }
+    m->scratch = scratch_on(m->device, m->scratch_msg);
     size_t o = 0, ob = 0;
     int K = cfg->n_in;
     for (int l = 0; l <= cfg->depth; ++l) {
@@ -461,6 +497,35 @@ dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, co
     forward(m, x_dev, (int)batch);
     MHIP(m, hipGetLastError());
     return infer_decode(m, m->out, batch, scale, flux_dev, err_est_dev);
+}
+
+int64_t dfhm_mlp_noalloc_max_batch(const dfhm_mlp *m)
+{
+    if (!m) return -1;
+    const size_t per_row = 2 * (size_t)m->cfg.width * sizeof(uint16_t) + kOutPad * sizeof(float);
+    return (int64_t)((kScratchBytes - 1024) / per_row);
+}
+
+dfhm_status dfhm_mlp_infer_noalloc(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch,
+                                   const float *scale, float *flux_dev, float *err_est_dev)
+{
+    dfhm_status st = infer_args(m, x_dev, batch, scale, flux_dev, err_est_dev);
+    if (st) return st;
+    if (batch > dfhm_mlp_noalloc_max_batch(m))
+        return mfail(m, DFHM_E_INVAL, "batch above the allocation-free limit (" +
+                                          std::to_string(dfhm_mlp_noalloc_max_batch(m)) + " rows)");
+    if (!m->scratch) return mfail(m, DFHM_E_DEVICE, "scratch not available: " + m->scratch_msg);
+    // [hidden A][hidden B][output], each 256-byte aligned; every element a
+    // kernel reads was written earlier in this call, so nothing is cleared
+    const size_t hid = ((size_t)batch * m->cfg.width * sizeof(uint16_t) + 255) / 256 * 256;
+    uint8_t *base = (uint8_t *)m->scratch;
+    uint16_t *h[2] = {(uint16_t *)base, (uint16_t *)(base + hid)};
+    float *y = (float *)(base + 2 * hid);
+    forward_into(m, (int)batch,
+                 [&](int l) { return l == 0 ? x_dev : (const uint16_t *)h[(l - 1) & 1]; },
+                 [&](int l) { return h[l & 1]; }, [](int) { return (uint16_t *)nullptr; }, y);
+    MHIP(m, hipGetLastError());
+    return infer_decode(m, y, batch, scale, flux_dev, err_est_dev);
 }
 
 dfhm_status dfhm_mlp_get_intermediate(dfhm_mlp *m, int32_t kind, int32_t layer, int64_t rows,

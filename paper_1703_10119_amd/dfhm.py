@@ -116,7 +116,8 @@ EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_zone_lin
            "dfhm_mlp_set_params", "dfhm_mlp_forward", "dfhm_mlp_gradients",
            "dfhm_mlp_train_step", "dfhm_mlp_last_error", "dfhm_mlp_destroy",
            "dfhm_mlp_features", "dfhm_mlp_decode", "dfhm_mlp_decode_ensemble",
-           "dfhm_mlp_get_intermediate", "dfhm_mlp_infer")
+           "dfhm_mlp_get_intermediate", "dfhm_mlp_infer", "dfhm_mlp_infer_noalloc",
+           "dfhm_mlp_noalloc_max_batch")
 
 _lib = None
 
@@ -197,6 +198,10 @@ def load(path: str = LIB_PATH):
               L.dfhm_mlp_features, L.dfhm_mlp_decode, L.dfhm_mlp_decode_ensemble,
               L.dfhm_mlp_infer, L.dfhm_mlp_get_intermediate):
         f.restype = C.c_int
+    L.dfhm_mlp_infer_noalloc.argtypes = [P, P, I64, P, P, P]
+    L.dfhm_mlp_infer_noalloc.restype = C.c_int
+    L.dfhm_mlp_noalloc_max_batch.argtypes = [P]
+    L.dfhm_mlp_noalloc_max_batch.restype = I64
     _lib = L
     return L
 

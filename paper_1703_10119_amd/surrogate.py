@@ -78,17 +78,21 @@ class MLP:
         self._check(_lib().dfhm_mlp_forward(self._h, x.data_ptr(), B, y.data_ptr()), "forward")
         return y
 
-    def infer(self, x, scale):
+    def infer(self, x, scale, noalloc=False):
         """Fluxes [B, 2] and predicted relative errors [B] of the flux head
-        (dfhm_mlp_infer); scale = 8 floats."""
+        (dfhm_mlp_infer, or dfhm_mlp_infer_noalloc); scale = 8 floats."""
         import torch
         B = x.shape[0]
         flux = torch.empty((B, 2), dtype=torch.float32, device=x.device)
         err = torch.empty(B, dtype=torch.float32, device=x.device)
         sc = np.ascontiguousarray(scale, np.float32)
-        self._check(_lib().dfhm_mlp_infer(self._h, x.data_ptr(), B, sc.ctypes.data_as(C.c_void_p), flux.data_ptr(),
+        fn = _lib().dfhm_mlp_infer_noalloc if noalloc else _lib().dfhm_mlp_infer
+        self._check(fn(self._h, x.data_ptr(), B, sc.ctypes.data_as(C.c_void_p), flux.data_ptr(),
                        err.data_ptr()), "infer")
         return flux, err
+
+    def noalloc_max_batch(self) -> int:
+        return int(_lib().dfhm_mlp_noalloc_max_batch(self._h))
 
     ACT, PRE, DZ = 0, 1, 2
 
