@@ -48,13 +48,13 @@ SHAPE = dict(aT=0.5, aM=3.0, bTM=0.1 * LV, cT=0.2, aC=2.0, eTM=0.0, fTM=CW)
 
 DAY = 86400.0
 
-# Largest dt/dx (s/m) the batches use.  With the nonlinear law the state
-# dependence of the coefficients, taken at level n, acts like an explicitly
-# treated advection term, and the DF update then diverges once dt/dx reaches
-# about 1e4 s/m whatever lambda is (shown by the oracle alone); at 5000 s/m
-# the most diffusive walls of a 65,536-wall batch (nu ~ 9x nominal) still
-# diverge, at 3333 s/m none do.  The paper's own grid (3.6 s, 1 mm) sits at
-# 3600 s/m.  Generators keep dx >= dt / this.
+# Largest dt/dx (s/m) the batches use.  With the conductivities taken at
+# level n, their state dependence enters a perturbation as an explicitly and
+# centrally treated transport term, and the DF update then has a
+# Courant-type limit on dt/dx whatever lambda is (shown by the oracle alone);
+# at 5000 s/m the most diffusive walls of a 65,536-wall batch (nu ~ 9x
+# nominal) still diverge, at 3333 s/m none do.  The paper's own grid (3.6 s,
+# 1 mm) sits at 3600 s/m.  Generators keep dx >= dt / this.
 DT_OVER_DX_MAX = 1.0 / 3.0e-4
 
 
