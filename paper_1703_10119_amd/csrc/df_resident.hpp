@@ -67,9 +67,13 @@ constexpr int kFaceNone = 6;
 template <typename R> struct WallRec {
     double flux[12];          // now q, g per side; Neumaier sums; compensations
     double surf[2][2][2];     // [parity][side][T, P] surface values of level n
-    double amb[2][2][2];      // [parity][side][T, P] ambient at t^n
+    double amb[2][2][4];      // [parity][side]: the surface exchange with the air of
+                              // t^n, A_q = h_T (T_inf - T ref) + L_v h_M (P_inf - P ref) + q_inf,
+                              // A_g = h_M (P_inf - P ref) + g_inf, then 4 dx A_q, 4 dx A_g
     double rot[2][12];        // per side: T mean, amp, RH mean, amp, phase sin/cos, step sin/cos
-    double bc[2][8];          // per side: dx (s / r), h_T, h_M, L_v h_M, g_inf, q_inf, T ref, area
+    double bc[2][8];          // per side: 2 dx h_T, h_T, h_M, L_v h_M, 2 dx h_M, 2 dx L_v h_M,
+                              // T ref, area (dx = s / r: the update is divided by r)
+    double src[2][4];         // per side: g_inf, q_inf, 4 dx
     R cc[4][4];               // per layer: c0 / r, cM0 / r, theta ref, Pv ref
     R fk[8][4];               // per entry: k0, kM0 (layer, interface with the next, none),
                               // theta ref, Pv ref
@@ -244,14 +248,19 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         }
         for (int side = 0; side < 2; ++side) {
             double *bc = X.bc[side];
-            bc[0] = W.dx;                       // s / r
+            const double d2 = 2.0 * W.dx;       // 2 s / r
+            bc[0] = d2 * W.hT[side];
             bc[1] = W.hT[side];
             bc[2] = W.hM[side];
             bc[3] = rc.Lv * W.hM[side];
-            bc[4] = W.ginf[side];
-            bc[5] = W.qinf[side];
+            bc[4] = d2 * W.hM[side];
+            bc[5] = d2 * (rc.Lv * W.hM[side]);
             bc[6] = Store<R>::tref(W);
             bc[7] = W.area;
+            X.src[side][0] = W.ginf[side];
+            X.src[side][1] = W.qinf[side];
+            X.src[side][2] = 4.0 * W.dx;
+            X.src[side][3] = 0.0;
         }
         const double rinv = 1.0 / W.r;
         for (int l = 0; l < 3; ++l) {
@@ -348,7 +357,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
             const int b = t * NPT + q;
-            Ta_[q] = Pa_[q] = Tb_[q] = Pb_[q] = 0;
+            // padding: a physical state (FP64 stores absolute values; FP32
+            // deviations, where 0 is the wall's initial state)
+            Ta_[q] = Tb_[q] = (R)(sizeof(R) == 8 && LAW == 0 ? 293.15 : 0.0);
+            Pa_[q] = Pb_[q] = (R)(sizeof(R) == 8 && LAW == 0 ? 1000.0 : 0.0);
             info[q] = kFaceNone << 13;
             offs[q] = (uint32_t)((kWalls + offsetof(WallRec<R>, cc) + sizeof(R) * 4 * 3) >> 4) |
                       ((uint32_t)((kWalls + offsetof(WallRec<R>, fk) + sizeof(R) * 4 * kFaceNone) >> 4) << 16);
@@ -410,8 +422,19 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 Ta = st[0] + st[1] * st[4];
                 Pa = (st[2] + st[3] * st[6]) * psat_th(Ta - 273.15);
             }
-            wr[amb_slot].amb[par][amb_side][0] = Ta;
-            wr[amb_slot].amb[par][amb_side][1] = Pa;
+            {
+                // the surface exchange with this air, in the storage frame
+                const double *bc = wr[amb_slot].bc[amb_side];
+                const double *sc = wr[amb_slot].src[amb_side];
+                const double dPa = Pa - (double)wr[amb_slot].cc[0][3];
+                const double Ag = fma(bc[2], dPa, sc[0]);
+                const double Aq = fma(bc[1], Ta - bc[6], fma(bc[3], dPa, sc[1]));
+                double *A = wr[amb_slot].amb[par][amb_side];
+                A[0] = Aq;
+                A[1] = Ag;
+                A[2] = sc[2] * Aq;
+                A[3] = sc[2] * Ag;
+            }
             if constexpr (EXT) {
                 double *sq = xr[amb_slot].rotq[amb_side];
                 const double qs = sq[0] + sq[1] * sq[2];
@@ -502,30 +525,36 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             }
             kX[q] = 0;
             const R thr = k0.th, pr = k0.p;
-            // a node without a right face (wall end, padding) has zero scales;
-            // its face state is its own, so that nothing from the next wall or
-            // from padding enters its arithmetic (and no NaN can leak in)
-            const bool live = (info[q] >> 13) != kFaceNone;
-            const R Tr = live ? (q + 1 < NPT ? Tn[q + 1 < NPT ? q + 1 : q] : Tr_nb) : Tn[q];
-            const R Pr = live ? (q + 1 < NPT ? Pn[q + 1 < NPT ? q + 1 : q] : Pr_nb) : Pn[q];
-            const R thn = thr + Tn[q];
-            const R thf = fma((R)0.5, Tn[q] + Tr, thr);
+            // a node without a right face (wall end, padding) has zero face
+            // scales; its face state, shared with the next wall's first node,
+            // a padding node (which holds a physical state) or the
+            // workgroup's end, is finite, so its face is zero
+            const R Tr = q + 1 < NPT ? Tn[q + 1 < NPT ? q + 1 : q] : Tr_nb;
+            const R Pr = q + 1 < NPT ? Pn[q + 1 < NPT ? q + 1 : q] : Pr_nb;
             const R Pf = fma((R)0.5, Pn[q] + Pr, pr);
-            // Magnus exponents of face and node (FP64: one shared reciprocal)
-            const R df = thf + (R)243.04, dn = thn + (R)243.04;
-            R af, an;
+            R phi;                                          // phi = P / Ps at the face
             if constexpr (sizeof(R) == 8) {
+                // Magnus denominators theta + 243.04 of face and node (the
+                // reference theta is -273.15: absolute storage), one shared
+                // reciprocal, and 1 / Ps = 2^(C0 + C1 / d).  The node's value
+                // goes through the shared reciprocal, so a node without a
+                // right face takes its own temperature as the face's: its
+                // result then does not depend on what lies to its right
+                // (the next wall, padding), to the last bit
+                const R Tf2 = (info[q] >> 13) != kFaceNone ? Tn[q] + Tr : (R)2 * Tn[q];
+                const R df = fma((R)0.5, Tf2, thr + (R)243.04);
+                const R dn = Tn[q] + (thr + (R)243.04);
                 const R inv = rcp_nr(df * dn);
-                af = (thf * dn) * inv;
-                an = (thn * df) * inv;
+                phi = Pf * exp2_bounded(fma((R)kMagC1 * dn, inv, (R)kMagC0));
+                phn[q] = (pr + Pn[q]) * exp2_bounded(fma((R)kMagC1 * df, inv, (R)kMagC0));
             } else {
-                af = div_nr(thf, df);
-                an = div_nr(thn, dn);
+                const R thn = thr + Tn[q];
+                const R thf = fma((R)0.5, Tn[q] + Tr, thr);
+                const R af = div_nr(thf, thf + (R)243.04);
+                const R an = div_nr(thn, thn + (R)243.04);
+                phi = (Pf * exp_bounded(-(R)17.625 * af)) * ps_inv;
+                phn[q] = ((pr + Pn[q]) * exp_bounded(-(R)17.625 * an)) * ps_inv;
             }
-            const R ef = exp_bounded(-(R)17.625 * af);
-            const R en = exp_bounded(-(R)17.625 * an);
-            const R phi = (Pf * ef) * ps_inv;               // phi = P / Ps
-            phn[q] = ((pr + Pn[q]) * en) * ps_inv;
             kT[q] = k0.a * fma(aT, phi, (R)1);
             kM[q] = k0.b * fma(aM * phi, phi, (R)1);
             SCHED_FENCE();
@@ -564,8 +593,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 ccT = c0.a * fma(cT, phi, (R)1);
                 ccM = c0.b * fma(aC, phi, (R)1);
                 ccX = fma(fTM, th, eTM) * ccM;
-                lX = bTM * lM;
-                kXq = bTM * kM[q];
+                lX = kXq = 0;           // k_TM = b_TM k_M on every face (below)
             }
             const R Tl = q > 0 ? Tn[q > 0 ? q - 1 : 0] : Tl_nb;
             const R Pl = q > 0 ? Pn[q > 0 ? q - 1 : 0] : Pl_nb;
@@ -575,9 +603,13 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             if (!(f & (3 << 8))) {
                 const R KM = lM + kM[q];
                 const R KT = lT + kT[q];
-                const R KX = lX + kXq;
+                const R SM = fma(kM[q], Pr, lM * Pl);
+                // the shape law's k_TM is b_TM k_M on every face, so its sums
+                // are b_TM times the moisture ones
+                const R KX = LAW == 1 ? lX + kXq : bTM * KM;
+                const R SX = LAW == 1 ? fma(kXq, Pr, lX * Pl) : bTM * SM;
                 const R dM = ccM + KM, dT = ccT + KT;
-                const R numM = fma(ccM - KM, Pm[q], (R)2 * fma(kM[q], Pr, lM * Pl));
+                const R numM = fma(ccM - KM, Pm[q], (R)2 * SM);
                 R inv = 0;
                 if constexpr (sizeof(R) == 8) {
                     inv = rcp_nr(dM * dT);
@@ -588,8 +620,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const R rhs = fma(ccT - KT, Tm[q],
                                   fma((R)2, fma(kT[q], Tr, lT * Tl),
                                       fma(ccX - KX, Pm[q],
-                                          fma(-(ccX + KX), Pnew,
-                                              (R)2 * fma(kXq, Pr, lX * Pl)))));
+                                          fma(-(ccX + KX), Pnew, (R)2 * SX))));
                 if constexpr (sizeof(R) == 8) Tnew = rhs * (dM * inv);
                 else Tnew = div_nr(rhs, dT);
             } else {
@@ -599,27 +630,25 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const double *bc = X.bc[side];
                 const R k_T = side == 0 ? kT[q] : lT;
                 const R k_M = side == 0 ? kM[q] : lM;
-                const R k_X = side == 0 ? kXq : lX;
+                const R k_X = LAW == 1 ? (side == 0 ? kXq : lX) : bTM * k_M;
                 const R Tnb = side == 0 ? Tr : Tl;
                 const R Pnb = side == 0 ? Pr : Pl;
-                const double Tinf = X.amb[par][side][0];
-                const double Pinf = X.amb[par][side][1];
-                const double tref = bc[6];
-                const R Tid = (R)(Tinf - tref);
-                const R Pid = (R)(Pinf - (double)pr);
-                const R d = (R)bc[0];                      // s / r
-                const R hT = (R)bc[1], hM = (R)bc[2];
-                const R hL = (R)bc[3];
-                double qsrc = bc[5];                          // constant + radiative
-                if constexpr (EXT) qsrc += xr[s].qx[par][side];
-                const R ginf = (R)bc[4], qinf = (R)qsrc;
-                const R gM = fma((R)2, k_M, (R)2 * d * hM);     // 2 r k + 2 s h (over r)
-                const R gT = fma((R)2, k_T, (R)2 * d * hT);
-                const R gX = fma((R)2, k_X, (R)2 * d * hL);
+                // the exchange with the air of t^n (ambient lanes, phase A)
+                const double *A = X.amb[par][side];
+                double Aq = A[0], Bq = A[2];
+                const double Ag = A[1], Bg = A[3];
+                if constexpr (EXT) {
+                    const double qx = xr[s].qx[par][side];   // radiative sources
+                    Aq += qx;
+                    Bq = fma(X.src[side][2], qx, Bq);
+                }
+                // 2 r k + 2 s h (over r) per field
+                const R gM = fma((R)2, k_M, (R)bc[4]);
+                const R gT = fma((R)2, k_T, (R)bc[0]);
+                const R gX = fma((R)2, k_X, (R)bc[5]);
                 const R dM = ccM + gM;
                 const R dT = ccT + gT;
-                const R numM = fma(ccM - gM, Pm[q],
-                                   fma((R)4 * k_M, Pnb, (R)4 * d * fma(hM, Pid, ginf)));
+                const R numM = fma(ccM - gM, Pm[q], fma((R)4 * k_M, Pnb, (R)Bg));
                 R inv = 0;
                 if constexpr (sizeof(R) == 8) {
                     inv = rcp_nr(dM * dT);
@@ -631,24 +660,24 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                               fma((R)4 * k_T, Tnb,
                               fma(ccX - gX, Pm[q],
                               fma(-(ccX + gX), Pnew,
-                              fma((R)4 * k_X, Pnb,
-                                  (R)4 * d * fma(hT, Tid, fma(hL, Pid, qinf)))))));
+                              fma((R)4 * k_X, Pnb, (R)Bq)))));
                 if constexpr (sizeof(R) == 8) Tnew = rhs * (dM * inv);
                 else Tnew = div_nr(rhs, dT);
                 // applied flux (FP64) and its compensated integral
                 const double dt = s_rc[0];
                 const double Ts = 0.5 * ((double)Tnew + (double)Tm[q]);
                 const double Ps = 0.5 * ((double)Pnew + (double)Pm[q]);
-                const double g = bc[2] * ((Pinf - (double)pr) - Ps) + bc[4];
-                const double qh = bc[1] * ((Tinf - tref) - Ts)
-                                + bc[3] * ((Pinf - (double)pr) - Ps) + qsrc;
+                const double g = fma(-bc[2], Ps, Ag);
+                const double qh = fma(-bc[1], Ts, fma(-bc[3], Ps, Aq));
                 double *fw = X.flux;
                 fw[side * 2] = qh;
                 fw[side * 2 + 1] = g;
                 neumaier_add(fw[4 + side * 2], fw[8 + side * 2], dt * qh);
                 neumaier_add(fw[5 + side * 2], fw[9 + side * 2], dt * g);
             }
-            if (!(f & (1 << 10))) { Tnew = 0; Pnew = 0; }
+            // padding nodes: the Table 1 law keeps them at zero (its faces
+            // test for them); under the shape law they keep a physical state
+            if (LAW == 1 && !(f & (1 << 10))) { Tnew = 0; Pnew = 0; }
             Tm[q] = Tnew;   // level n-1 is no longer needed by node q
             Pm[q] = Pnew;
             SCHED_FENCE();

@@ -198,6 +198,34 @@ __device__ __forceinline__ double exp_bounded(double a)
 }
 __device__ __forceinline__ float exp_bounded(float a) { return __expf(a); }
 
+// 2^y for |y| well inside the FP64 exponent range: y = k + f with k the
+// nearest integer (f = y - k is exact), |f| <= 1/2, then the degree-9
+// polynomial that interpolates 2^f at the 10 Chebyshev nodes of [-1/2, 1/2]
+// (coefficients computed in 60-digit arithmetic and rounded to FP64;
+// relative error on the interval 1.8e-14) and a scaling by 2^k.
+__device__ __forceinline__ double exp2_bounded(double y)
+{
+    const double k = rint(y);
+    const double f = y - k;
+    double p = 1.0205905413765595e-07;
+    p = fma(p, f, 1.325964524488711e-06);
+    p = fma(p, f, 1.5252672924850737e-05);
+    p = fma(p, f, 0.0001540343375125101);
+    p = fma(p, f, 0.0013333558200794592);
+    p = fma(p, f, 0.009618129193934313);
+    p = fma(p, f, 0.05550410866465167);
+    p = fma(p, f, 0.2402265069564034);
+    p = fma(p, f, 0.6931471805599462);
+    p = fma(p, f, 1.0000000000000135);
+    return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
+// The Magnus saturation pressure in the form 1 / Ps(theta) = 2^(C0 + C1 / d),
+// d = theta + 243.04: with 17.625 theta / d = 17.625 - 17.625 x 243.04 / d,
+// C1 = 17.625 x 243.04 / ln 2 and C0 = -17.625 / ln 2 - log2(610.94).
+constexpr double kMagC1 = 6179.899623251146;
+constexpr double kMagC0 = -34.6823869863494;
+
 // ------------------------------------------------- Table 1 material law
 // The load-bearing material of Sec. 6 (Table 1), read as follows (every
 // coefficient of Table 2 is reproduced within 1.5 % at 20 degC):
