@@ -283,6 +283,7 @@ dfhm_status dfhm_autotune(dfhm_ctx *ctx, int32_t probe_steps);
  * field and sub-iteration, moisture first, heat with the new vapour
  * pressure.  A sub-iteration loop stops when the largest change of T and of
  * Pv is at most eta times the largest |T| and |Pv|, or after max_iters.  FP64,
+ * either material law (dfhm_implicit_config.law),
  * walls with the outdoor air on both sides (zones are not coupled), from the
  * walls' uniform initial state; no start-up step (two-level scheme).  For
  * measuring what the explicit DF scheme saves against it.
@@ -293,9 +294,11 @@ typedef struct {
     double theta;          /* in [0.5, 1] */
     double eta;            /* > 0, relative fixed-point tolerance */
     int32_t max_iters;     /* >= 1 sub-iterations per step */
-    int32_t reserved;
+    int32_t law;           /* DFHM_LAW_SHAPE or DFHM_LAW_TABLE1 (the material
+                              of Sec. 6 and Table 3) */
     double Lv;             /* 0 -> 2.5e6 J/kg */
     void *stream;          /* hipStream_t or NULL */
+    double cw;             /* 0 -> 4180 J/(kg K) (c_TM of the Table 1 law) */
 } dfhm_implicit_config;
 /* Walls as for dfhm_create (side 1 uses T_amb[1] / RH_amb[1]).  Allocates
  * 7 doubles per node (walls grouped by 64, each group padded to its longest

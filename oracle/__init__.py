@@ -274,12 +274,14 @@ class RefSim:
 
 
 def implicit_run(walls: dict, w: int, dt: float, Lv: float, nsteps: int,
-                 theta: float = 0.5, eta: float = 1e-12):
-    """Theta-scheme comparator with fixed-point sub-iterations on wall ``w``.
+                 theta: float = 0.5, eta: float = 1e-12, law: int = 0, cw: float = 4180.0):
+    """Theta-scheme comparator with fixed-point sub-iterations on wall ``w``
+    (law 0: the shape law; 1: the Table 1 material).
 
     Returns (T, P, mean fixed-point iterations per step)."""
     one = {k: (v[w:w + 1] if hasattr(v, "__len__") else v) for k, v in walls.items()}
     arr = _walls_struct(one)
+    arr[0].law, arr[0].Lv, arr[0].cw = int(law), float(Lv), float(cw)
     nx = int(walls["nx"][w])
     T = np.empty(nx)
     P = np.empty(nx)

@@ -49,6 +49,9 @@ __global__ void k_imp_init(const WallDev *__restrict__ walls, const ImpGroup *__
 // the coefficient evaluations inside the sweeps read no global memory.
 struct ImpLaw {
     const double *p;     // &s_law[0][lane]
+    int law;             // 0: shape law (from p); 1: Table 1 material (from W)
+    const WallDev *W;
+    double Lv, cw;
     __device__ __forceinline__ double operator()(int la, int k) const
     {
         return p[(la * L_COUNT + k) * kImpLanes];
@@ -69,6 +72,10 @@ __device__ __forceinline__ ImpK imp_law_k(const ImpLaw &m, int la, double phi)
 }
 __device__ __forceinline__ ImpK imp_face(const ImpLaw &m, int la, int lb, double T, double P)
 {
+    if (m.law == 1) {          // Table 1 material (layer scales from the descriptor)
+        const KCoef<double> k = t1_face_k<double>(*m.W, la, lb, T - 273.15, P, m.Lv);
+        return {k.kT, k.kM, k.kX};
+    }
     const double phi = P / psat_th(T - 273.15);
     const ImpK a = imp_law_k(m, la, phi);
     if (la == lb) return a;
@@ -78,6 +85,10 @@ __device__ __forceinline__ ImpK imp_face(const ImpLaw &m, int la, int lb, double
 __device__ __forceinline__ ImpC imp_node(const ImpLaw &m, int la, double T, double P)
 {
     const double th = T - 273.15;
+    if (m.law == 1) {
+        const CCoef<double> c = t1_law_c<double>(m.W->lay[la], th, P, m.cw);
+        return {c.cT, c.cM, c.cX};
+    }
     const double phi = P / psat_th(th);
     ImpC c;
     c.cT = m(la, L_C0) * (1.0 + m(la, L_CT) * phi);
@@ -91,7 +102,7 @@ __device__ __forceinline__ ImpC imp_node(const ImpLaw &m, int la, double T, doub
 __global__ void __launch_bounds__(kImpLanes)
 k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ groups, ImpArrays A,
            int64_t n, double dt, double theta, double eta, int max_it, double Lv,
-           int64_t *__restrict__ iters)
+           int law_id, double cw, int64_t *__restrict__ iters)
 {
     __shared__ double s_law[kMaxLayers * L_COUNT][kImpLanes];
     const ImpGroup G = groups[blockIdx.x];
@@ -101,7 +112,7 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
     const WallDev &W = walls[w];
     const int nx = W.nx;
     for (int q = 0; q < kMaxLayers * L_COUNT; ++q) s_law[q][lane] = W.lay[q / L_COUNT][q % L_COUNT];
-    const ImpLaw law{&s_law[0][lane]};
+    const ImpLaw law{&s_law[0][lane], law_id, &W, Lv, cw};
     // first node of layers 1 and 2 (node j is in the first layer whose right
     // end is >= x_j), so that a node's layer is two compares
     int jb1 = nx, jb2 = nx;

@@ -144,15 +144,16 @@ __device__ __forceinline__ Quad<R> lds_scales(const unsigned char *base, int off
     return q;
 }
 
-// Register budget (waves per SIMD).  Up to 4 nodes per lane: four waves
-// (at most 128 VGPRs; the few loop-invariant values that do not fit are
-// re-read from the L1-resident spill area each step, which costs far less
-// than the waves that hide the latency of the FP64 pipeline and of LDS),
-// except where the FP64 step carries more code (the Table 1 law, zones):
-// three.  8 nodes per lane: two waves.  (Measured on the 65,536 x 1001
-// batch: FP64 2 -> 4 waves +27 %.  FP32 once measured 6 % slower with four
-// waves than with three; after the ambient lanes left the first wave it is
-// 6 % faster.)
+// Register budget (waves per SIMD).  FP64 with up to 4 nodes per lane:
+// three waves (168 VGPRs).  At four (128 VGPRs) the FP64 step loop fits only
+// by spilling loop-invariant values -- chiefly the exponential's polynomial
+// coefficients, which the compiler keeps in registers -- and every lane
+// writes that spill area once per launch: 2.8 GB per launch of the 65,536 x
+// 1001 batch.  Measured there: three waves 0.257 ms per step in 20-step
+// launches against 0.282 with four, and 0.8 % slower in 1000-step launches.
+// FP32 with up to 4 nodes per lane, and 512-lane workgroups: four waves
+// (FP32 measured against three: +6 % on the 65,536 x 1001 batch, +2-4 % with
+// zones).  8 nodes per lane: two waves.  (FP64 2 -> 4 waves once gave +27 %, before the LDS scale tables.)
 // Kernel variants: only what a launch needs is compiled in, since every
 // extra line of the step loop competes for the registers of the node work.
 constexpr int kModePlain = 0;   // walls without zones or radiative sources
@@ -161,15 +162,10 @@ constexpr int kModeExt = 2;     // radiative sources and / or linked zones
 
 template <typename R, int NPT, int NT, int MODE, int LAW> constexpr int res_waves_per_eu()
 {
-    // the Table 1 law's FP64 node work is larger: three waves (measured
-    // 1.5 % faster than four on its 65,536 x 1001 batch, two 0.5 % slower);
-    // so is the FP64 zone and extended code: three in workgroups of up to 256
-    // lanes (measured against four: +7 % on the building batch, +11 % with
-    // radiation; 512-lane workgroups would lose one of two per CU); otherwise
-    // four for up to 4 nodes per lane, FP32 included (measured against three:
-    // +6 % on the 65,536 x 1001 batch, +2-4 % with zones)
-    if (sizeof(R) == 8 && NPT <= 4 && (LAW == 1 || (MODE != kModePlain && NT <= 256))) return 3;
-    return NPT > 4 ? 2 : 4;
+    if (NPT > 4) return 2;
+    // 512-lane workgroups keep four (three would leave room for only one
+    // workgroup per CU)
+    return sizeof(R) == 8 && NT <= 256 ? 3 : 4;
 }
 
 // LAW: 0 = the shape law (scales x the launch's common shape factors),
@@ -420,7 +416,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 Pa = rr[amb_zone].air[par][1];
             } else {
                 Ta = st[0] + st[1] * st[4];
-                Pa = (st[2] + st[3] * st[6]) * psat_th(Ta - 273.15);
+                // Ps = 2^-(C0 + C1 / (theta + 243.04)): the node work's
+                // exponential, whose coefficients are in registers already
+                const double d = Ta - (273.15 - 243.04);
+                Pa = (st[2] + st[3] * st[6]) * exp2_bounded(-fma(kMagC1, rcp_nr(d), kMagC0));
             }
             {
                 // the surface exchange with this air, in the storage frame
@@ -467,7 +466,8 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             const int64_t slot = (int64_t)floor(tt / Rm.sched_dt) % Rm.n_sched;
             const double go = sched_go[Rm.sched_off + slot], Qh = sched_qh[Rm.sched_off + slot];
             const double Tout = sine_at(Rm.Tout, tt);
-            const double Pout = sine_at(Rm.RHout, tt) * psat_th(Tout - 273.15);
+            const double Pout = sine_at(Rm.RHout, tt) *
+                                exp2_bounded(-fma(kMagC1, rcp_nr(Tout - (273.15 - 243.04)), kMagC0));
             double G = go + gv * (Pout - Pa) / Pv_ref;
             double Q = Qh + Lv * go + gv * cma * (Tout - Ta) + Lv * gv * (Pout - Pa) / Pv_ref;
             double S4 = 0.0;            // sum of T_w^4 over the zone's surfaces
@@ -704,10 +704,13 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     // ---- write back: level n0+k and n0+k-1, fluxes, zone air
     const ResIO O = *io;
     const int64_t nend = n0 + ksteps;
-    R *Tw_cur = (R *)O.T[nend & 1];
-    R *Pw_cur = (R *)O.P[nend & 1];
-    R *Tw_prv = (R *)O.T[(nend & 1) ^ 1];
-    R *Pw_prv = (R *)O.P[(nend & 1) ^ 1];
+    // pointers picked by selects, not by indexing (an indexed local array
+    // would live in scratch memory)
+    const bool odd = (nend & 1) != 0;
+    R *Tw_cur = (R *)(odd ? O.T[1] : O.T[0]);
+    R *Pw_cur = (R *)(odd ? O.P[1] : O.P[0]);
+    R *Tw_prv = (R *)(odd ? O.T[0] : O.T[1]);
+    R *Pw_prv = (R *)(odd ? O.P[0] : O.P[1]);
     int nonfinite = 0;
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {

@@ -1205,7 +1205,8 @@ dfhm_status dfhm_implicit_create(const dfhm_implicit_config *cfg, const dfhm_wal
     *out = nullptr;
     if (!cfg || !walls || n_walls < 1) return DFHM_E_INVAL;
     if (!(std::isfinite(cfg->dt_s) && cfg->dt_s > 0.0) || !(cfg->theta >= 0.5 && cfg->theta <= 1.0) ||
-        !(cfg->eta > 0.0) || cfg->max_iters < 1)
+        !(cfg->eta > 0.0) || cfg->max_iters < 1 ||
+        (cfg->law != DFHM_LAW_SHAPE && cfg->law != DFHM_LAW_TABLE1))
         return DFHM_E_INVAL;
     for (int64_t i = 0; i < n_walls; ++i)
         if (!check_wall(walls[i], i).empty()) return DFHM_E_INVAL;
@@ -1213,6 +1214,7 @@ dfhm_status dfhm_implicit_create(const dfhm_implicit_config *cfg, const dfhm_wal
     if (!ic) return DFHM_E_NOMEM;
     ic->cfg = *cfg;
     ic->cfg.Lv = orz(cfg->Lv, 2.5e6);
+    ic->cfg.cw = orz(cfg->cw, 4180.0);
     ic->stream = (hipStream_t)cfg->stream;
     ic->nw = n_walls;
     ic->walls.resize(n_walls);
@@ -1265,7 +1267,8 @@ dfhm_status dfhm_implicit_step_n(dfhm_implicit *ic, int64_t n_steps)
     for (int64_t k = 0; k < n_steps; ++k) {
         hipLaunchKernelGGL(k_imp_step, dim3(ic->ngroups), dim3(kImpLanes), 0, ic->stream, ic->d_walls,
                            ic->d_groups, ic->A, ic->n, ic->cfg.dt_s, ic->cfg.theta, ic->cfg.eta,
-                           (int)ic->cfg.max_iters, ic->cfg.Lv, ic->d_iters);
+                           (int)ic->cfg.max_iters, ic->cfg.Lv, (int)ic->cfg.law, ic->cfg.cw,
+                           ic->d_iters);
         ic->n += 1;
     }
     if (hipGetLastError() != hipSuccess) { ic->err = "kernel launch failed"; return DFHM_E_DEVICE; }

@@ -81,8 +81,8 @@ class Info(C.Structure):
 class ImplicitConfig(C.Structure):
     """dfhm_implicit_config"""
     _fields_ = [("dt_s", C.c_double), ("theta", C.c_double), ("eta", C.c_double),
-                ("max_iters", C.c_int32), ("reserved", C.c_int32), ("Lv", C.c_double),
-                ("stream", C.c_void_p)]
+                ("max_iters", C.c_int32), ("law", C.c_int32), ("Lv", C.c_double),
+                ("stream", C.c_void_p), ("cw", C.c_double)]
 
 
 class MlpConfig(C.Structure):
@@ -468,11 +468,13 @@ class Implicit:
     sub-iterations) on the current HIP device: dfhm_implicit_*."""
 
     def __init__(self, walls: dict, dt: float, theta: float = 1.0, eta: float = 1e-10,
-                 max_iters: int = 200, Lv: float = 0.0, stream=None):
+                 max_iters: int = 200, Lv: float = 0.0, stream=None, law: int = 0,
+                 cw: float = 0.0):
         import torch
         L = load()
         c = ImplicitConfig()
         c.dt_s, c.theta, c.eta, c.max_iters, c.Lv = float(dt), float(theta), float(eta), int(max_iters), float(Lv)
+        c.law, c.cw = int(law), float(cw)
         c.stream = torch.cuda.current_stream().cuda_stream if stream is None else stream
         self.W = len(walls["nx"])
         self.nx = np.asarray(walls["nx"], np.int64)

@@ -175,7 +175,7 @@ def features(wall_idx, t, sines_d, params_d, desc):
     return x
 
 
-def generate(walls, precision=dfhm.FP32, dt=1.0, spinup_s=SPINUP_S, n_windows=N_WINDOWS):
+def generate(walls, precision=dfhm.FP64, dt=1.0, spinup_s=SPINUP_S, n_windows=N_WINDOWS):
     """Run the DF solver on a wall batch and return the window targets.
 
     Returns dict(flux [W, n_windows, 2] side-1 mean (heat W/m2, vapour
@@ -312,41 +312,148 @@ def errors(pred, truth):
 
 def calibrate_tau(nets, walls, data, desc, targets, target=0.01, q=0.99):
     """Largest fallback threshold (predicted relative error) whose p-q error
-    after fallback is <= target on the given (calibration) walls."""
+    after fallback is <= target on the given (calibration) walls; a fallback
+    sample takes the DF value of `data`, which the fallback solve reproduces
+    (checked where the pipeline runs, in `serve`)."""
     for tau in np.geomspace(0.1, 0.0005, 40):
         pred, fb, _ = predict(nets, walls, data["t"], desc, targets, tau)
         e = errors(pred, data["flux"]).max(axis=2)
-        e[fb] = 0.0                      # fallback samples are the DF solve itself
+        e[fb] = 0.0
         if np.quantile(e, q) <= target:
             return float(tau)
     return None
 
 
-def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=16384,
-          target=0.01, q=0.99, cal_margin=0.9, seed=1, n_nets=3, log=None):
-    """Train on DF histories, calibrate the fallback threshold on one set of
-    walls and measure error and speed-up on another (all C2-type walls:
-    30 cm, 1001 nodes, dt = 1 s, different generator seeds).  With n_nets > 1
-    an ensemble of networks (seeds seed, seed + 1, ...) is trained on the
-    same data and its mean flux and mean predicted error are used; the MLP
-    time then covers every member.
-
-    Error: |q_MLP - q_DF| / RMS over the windows of q_DF, per wall and
-    field; a sample's error is the larger of its two fields, and fallback
-    samples take the DF value (error 0).  tau is the largest threshold whose
-    q-quantile error on the calibration walls is <= cal_margin * target.
-    Speed-up = DF time / (MLP time + DF time of the fallback samples), with
-    the DF cost of one sample taken at the measured batched DF throughput:
-      warm: 600 steps (the DF state is carried from the previous window),
-      cold: 48 h + 10 min of steps (the state is rebuilt from scratch)."""
+def _timed(fn):
     import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def serve(nets, walls, truth, desc, targets, tau, windows, dt=1.0, precision=dfhm.FP64):
+    """The surrogate as a solver, executed and timed against the DF solve.
+
+    A query asks for the next-window mean interior fluxes of every wall at
+    window k.  The DF solve answers it by running all walls from their
+    initial state to the end of window k (timed once, in one run with
+    checkpoints at the query windows).  The surrogate pipeline answers it
+    with the networks (feature rows, forward passes, ensemble decode with
+    its error estimate), then runs the DF solver from the initial state to
+    the end of window k on just the walls whose estimate exceeds tau, and
+    takes their DF fluxes.  Both times include creating the solver and
+    reading the fluxes back.  Every answer is judged against `truth` (the
+    continuous DF run): |answer - truth| / RMS over the windows of the
+    truth, per wall and field; the fallback answers are compared too."""
+    import torch
+    W = len(walls["nx"])
+    cfg = wl.default_config(dt=dt)
+    wsteps = int(round(WINDOW_S / dt))
+    spin = int(round(SPINUP_S / dt))
+    windows = sorted(int(k) for k in windows)
+
+    def df_to(sub, ks):
+        """DF on wall set `sub` to the end of each window in ks; returns the
+        window fluxes [len(sub), len(ks), 2] and the elapsed time at each
+        window's end (from before the solver is created)."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = dfhm.Solver(sub, cfg, precision=precision, schedule=dfhm.SCHED_RESIDENT)
+        n = 0
+        out = np.empty((len(sub["nx"]), len(ks), 2))
+        at = []
+        for i, k in enumerate(ks):
+            start = spin + k * wsteps
+            s.step(start - n)
+            _, I0 = s.fluxes()
+            s.step(wsteps)
+            _, I1 = s.fluxes()
+            n = start + wsteps
+            out[:, i, :] = (I1[:, 1, :] - I0[:, 1, :]) / (wsteps * dt)
+            at.append(time.perf_counter() - t0)
+        s.close()
+        return out, at
+
+    base, t_base = df_to(walls, windows)
+    rms = np.sqrt(np.mean(truth["flux"] ** 2, axis=1))                 # [W, 2]
+    sines, params = wall_inputs(walls)
+    dev = "cuda"
+    sines_d = torch.tensor(sines, device=dev)
+    params_d = torch.tensor(params, device=dev)
+    wall_of = torch.arange(W, device=dev, dtype=torch.int32)
+    sc = np.ascontiguousarray(targets.scale8())
+    rows = []
+    for i, k in enumerate(windows):
+        t_k = torch.full((W,), SPINUP_S + WINDOW_S * k, dtype=torch.float64, device=dev)
+
+        def network():
+            x = features(wall_of, t_k, sines_d, params_d, desc)
+            ys = [net.forward(x) for net in nets]
+            ptrs = (C.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
+            flux = torch.empty((W, 2), dtype=torch.float32, device=dev)
+            fb = torch.empty(W, dtype=torch.uint8, device=dev)
+            st = _lib().dfhm_mlp_decode_ensemble(ptrs, len(ys), W, sc.ctypes.data_as(C.c_void_p),
+                                                 float(tau), flux.data_ptr(), fb.data_ptr(), _stream())
+            if st != 0:
+                raise dfhm.DfhmError(st, "dfhm_mlp_decode_ensemble")
+            return flux.cpu().numpy().astype(np.float64), fb.cpu().numpy().astype(bool)
+
+        network()                                   # warm-up (first launch of the kernels)
+        (flux, fb), t_net = _timed(network)
+        idx = np.nonzero(fb)[0]
+        t_fb = 0.0
+        if len(idx):
+            fl, at = df_to(wl.subset(walls, idx), [k])
+            t_fb = at[0]
+            fb_err = np.abs(fl[:, 0, :] - truth["flux"][idx, k, :]) / rms[idx]
+            flux[idx] = fl[:, 0, :]
+        else:
+            fb_err = np.zeros((0, 2))
+        e = (np.abs(flux - truth["flux"][:, k, :]) / rms).max(axis=1)
+        base_err = np.abs(base[:, i, :] - truth["flux"][:, k, :]) / rms
+        rows.append(dict(window=k, t_df=t_base[i], t_net=t_net, t_fallback=t_fb,
+                         speedup=t_base[i] / (t_net + t_fb), fallback_fraction=len(idx) / W,
+                         err_p50=float(np.median(e)), err_p99=float(np.quantile(e, 0.99)),
+                         err_max=float(e.max()), fallback_err_max=float(fb_err.max()) if len(idx) else 0.0,
+                         df_rerun_err_max=float(base_err.max()),
+                         speedup_network_only=t_base[i] / t_net))
+    tot_df = sum(r["t_df"] for r in rows)
+    tot_sur = sum(r["t_net"] + r["t_fallback"] for r in rows)
+    return dict(windows=rows, speedup=tot_df / tot_sur,
+                speedup_network_only=tot_df / sum(r["t_net"] for r in rows),
+                fallback_fraction=float(np.mean([r["fallback_fraction"] for r in rows])),
+                err_p99=max(r["err_p99"] for r in rows), err_max=max(r["err_max"] for r in rows),
+                fallback_err_max=max(r["fallback_err_max"] for r in rows),
+                df_seconds=tot_df, surrogate_seconds=tot_sur, walls=W)
+
+
+def study(n_train=65536, n_cal=2048, n_test=8192, epochs=60, lr=2e-3, batch=16384,
+          target=0.01, q=0.99, cal_margin=0.9, seed=1, n_nets=3,
+          windows=(0, 52, 104, 155), log=None):
+    """Train on DF histories, calibrate the fallback threshold on one set of
+    walls, and run the executed pipeline (`serve`) on another (all C2-type
+    walls: 30 cm, 1001 nodes, dt = 1 s, different generator seeds; FP64 DF
+    targets and fallback).  With n_nets > 1 an ensemble of networks (seeds
+    seed, seed + 1, ...) is trained on the same data and its mean flux and
+    mean predicted error are used; the network time covers every member.
+
+    Error: |q - q_DF| / RMS over the windows of q_DF, per wall and field; a
+    sample's error is the larger of its two fields.  tau is the largest
+    threshold whose q-quantile error on the calibration walls is <=
+    cal_margin * target.  The raw errors (no fallback) are reported over all
+    windows of the held-out walls, and the FP32 DF solve's own error against
+    the FP64 targets on the calibration walls."""
     say = log or (lambda *a: None)
     tr = wl.uniform_batch(n_train, seed=505)
     ca = wl.uniform_batch(n_cal, seed=515)
     te = wl.uniform_batch(n_test, seed=516)
     d_tr = generate(tr)
-    say(f"DF data: {n_train} walls x {d_tr['steps']} steps in {d_tr['df_seconds']:.1f} s")
+    say(f"DF data (FP64): {n_train} walls x {d_tr['steps']} steps in {d_tr['df_seconds']:.1f} s")
     d_ca = generate(ca)
+    d_ca32 = generate(ca, precision=dfhm.FP32)
+    e32 = errors(d_ca32["flux"], d_ca["flux"])
     d_te = generate(te)
     targets = Targets(d_tr["flux"])
     _, params = wall_inputs(tr)
@@ -364,32 +471,24 @@ def study(n_train=65536, n_cal=2048, n_test=4096, epochs=60, lr=2e-3, batch=1638
     say("calibrating the fallback threshold")
     tau = calibrate_tau(nets, ca, d_ca, desc, targets, target=cal_margin * target, q=q)
     predict(nets, te, d_te["t"], desc, targets, 10.0)           # warm-up
-    pred, fb, mlp_s = predict(nets, te, d_te["t"], desc, targets, tau if tau else 1e-30)
+    pred, _, mlp_s = predict(nets, te, d_te["t"], desc, targets, 10.0)
     e_raw = errors(pred, d_te["flux"]).max(axis=2)
-    e = e_raw.copy()
-    e[fb] = 0.0
-    n_samp = e.size
-    f = float(fb.mean())
-    # DF cost per sample at the measured throughput of the held-out run
-    per_update = d_te["df_seconds"] / d_te["cell_updates"]
-    nodes = float(wl.total_nodes(te)) / n_test
-    warm_sample = per_update * nodes * d_te["window_steps"]
-    cold_steps = int(round((SPINUP_S + WINDOW_S) / 1.0))
-    cold_sample = per_update * nodes * cold_steps
-    df_warm = n_samp * warm_sample
-    df_cold = n_samp * cold_sample
-    flops = 2.0 * n_params * n_samp * n_nets     # multiply-adds of the forward passes
+    say(f"serving {len(windows)} query windows of {n_test} walls (tau {tau})")
+    sv = serve(nets, te, d_te, desc, targets, tau if tau else 1e-30, windows)
+    flops = 2.0 * n_params * e_raw.size * n_nets     # multiply-adds of the forward passes
     for net in nets:
         net.close()
     return dict(
-        tau=tau, fallback_fraction=f, samples=n_samp,
-        err_p50=float(np.median(e)), err_p99=float(np.quantile(e, q)), err_max=float(e.max()),
+        tau=tau, fallback_fraction=sv["fallback_fraction"], speedup=sv["speedup"],
+        speedup_network_only=sv["speedup_network_only"], err_p99=sv["err_p99"],
+        err_max=sv["err_max"], fallback_err_max=sv["fallback_err_max"],
+        serve_windows=sv["windows"], df_seconds=sv["df_seconds"],
+        surrogate_seconds=sv["surrogate_seconds"],
         raw_err_p50=float(np.median(e_raw)), raw_err_p99=float(np.quantile(e_raw, q)),
-        mlp_seconds=mlp_s, mlp_tflops=flops / mlp_s / 1e12,
-        df_warm_seconds=df_warm, df_cold_seconds=df_cold,
-        speedup_warm=df_warm / (mlp_s + f * df_warm),
-        speedup_cold=df_cold / (mlp_s + f * df_cold),
-        speedup_no_fallback_warm=df_warm / mlp_s,
+        raw_frac_above_target=float(np.mean(e_raw > target)),
+        fp32_df_err_p99=[float(np.quantile(e32[..., f], 0.99)) for f in range(2)],
+        fp32_df_err_max=[float(e32[..., f].max()) for f in range(2)],
+        mlp_seconds=mlp_s, mlp_tflops=flops / mlp_s / 1e12, samples=int(e_raw.size),
         train_seconds=fit["seconds"], train_samples=fit["samples"],
         train_tflops=3.0 * 2.0 * n_params * fit["samples"] / fit["seconds"] / 1e12,
         data_seconds=d_tr["df_seconds"], n_train=n_train, n_cal=n_cal, n_test=n_test,

@@ -205,6 +205,33 @@ def table1_batch(n_walls: int, seed: int = 707, nx: int = 1001, L: float = 0.3,
     return w
 
 
+def paper_wall_batch(n_walls: int, seed: int = 808, nx: int = 101) -> dict:
+    """The wall of Sec. 4 and Table 3 (run with cfg["law"] = 1): 10 cm of the
+    Table 1 material (scales 1), nx nodes, h_T = 25 / 8 W/(m2 K) and h_M =
+    2e-7 / 3e-8 s/m outside / inside, 20 degC and 50 % inside and initially.
+    The paper's outdoor series exist only as figures; each wall sees
+    T = 293.15 + 10 sin(2 pi t / 24 h + a) K and RH = 0.5 + 0.2 sin(2 pi t /
+    12 h + b), with phases a, b drawn uniformly (one wall per phase pair, so
+    that a batch is not one wall repeated)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W = int(n_walls)
+    w = _empty_walls(W)
+    w["nx"][:] = nx
+    w["n_layers"][:] = 1
+    for name in ("k0", "kM0", "c0", "cM0"):
+        w["layer"][:, 0, LAYER_FIELDS.index(name)] = 1.0
+    w["layer"][:, 0, LAYER_FIELDS.index("thick")] = 0.1
+    w["hT"][:] = (25.0, 8.0)
+    w["hM"][:] = (2e-7, 3e-8)
+    _sine(w["Tamb"][:, 0], 293.15, 10.0, DAY, rng.uniform(0.0, 2 * math.pi, W))
+    _sine(w["RHamb"][:, 0], 0.5, 0.2, DAY / 2, rng.uniform(0.0, 2 * math.pi, W))
+    _sine(w["Tamb"][:, 1], 293.15, 0.0, DAY, 0.0)
+    _sine(w["RHamb"][:, 1], 0.5, 0.0, DAY / 2, 0.0)
+    w["T0"][:] = 293.15
+    w["RH0"][:] = 0.5
+    return w
+
+
 def _cap_nodes(w: dict, dx_min: float):
     """Limit Nx so that dx >= dx_min (at least 3 nodes)."""
     L = np.array([w["layer"][i, :w["n_layers"][i], 0].sum() for i in range(len(w["nx"]))])

@@ -104,3 +104,20 @@ def test_incident_radiation_matches_oracle():
             Tr, Pr, _ = oracle.implicit_run(walls, w, 60.0, wl.LV, 120, theta=theta, eta=1e-12)
             assert rel(T, Tr) <= TOL and rel(P, Pr) <= TOL, (theta, w, rel(T, Tr), rel(P, Pr))
         ic.close()
+
+
+def test_table1_walls_match_oracle():
+    """The Table 1 material (the paper's Table 3 wall: 10 cm, 101 nodes) at
+    dt = 3.6 s, Euler implicit and Crank-Nicolson, 60 steps."""
+    walls = wl.paper_wall_batch(66, seed=31)
+    for theta in (1.0, 0.5):
+        ic = dfhm.Implicit(walls, dt=3.6, theta=theta, eta=1e-12, max_iters=200, law=1)
+        ic.step(60)
+        for w in (0, 40, 65):
+            T, P = ic.fields(w)
+            Tr, Pr, it = oracle.implicit_run(walls, w, 3.6, wl.LV, 60, theta=theta, eta=1e-12,
+                                             law=1, cw=wl.CW)
+            eT, eP = rel(T, Tr), rel(P, Pr)
+            print(f"Table 1 law, theta={theta} wall {w}: T {eT:.2e} P {eP:.2e} ({it:.2f} sub-iterations)")
+            assert eT <= TOL and eP <= TOL, (w, eT, eP)
+        ic.close()
