@@ -103,23 +103,46 @@ struct ResIO {
     int *bad;
 };
 
-// Dynamic LDS layout of one workgroup for nt lanes, mw walls and mr zones:
-// halos and faces need one buffer each (a step's reads of them end before the
-// barrier that precedes their next write).
-// (The Table 1 law keeps a third lane-boundary face value, k_TM.)
-template <typename R> __host__ __device__ constexpr size_t res_off_rc(int nt, int law)
+// Dynamic LDS layout of one workgroup for nt lanes of npt nodes, mw walls and
+// mr zones: FP32 first keeps the low parts of its compensated levels (two
+// levels x two fields x npt per lane, private to the lane); then the halos
+// and faces, one buffer each (a step's reads of them end before the barrier
+// that precedes their next write).  (The Table 1 law keeps a third
+// lane-boundary face value, k_TM.)
+template <typename R> __host__ __device__ constexpr size_t res_off_halo(int nt, int npt)
 {
-    return ((sizeof(R) * (law ? 7 : 6) * (size_t)nt) + 15) & ~(size_t)15;
+    return sizeof(R) == 4 ? (size_t)16 * nt * npt : 0;
 }
-template <typename R> __host__ __device__ constexpr size_t res_off_walls(int nt, int law)
+template <typename R> __host__ __device__ constexpr size_t res_off_rc(int nt, int npt, int law)
 {
-    return res_off_rc<R>(nt, law) + 64;
+    return res_off_halo<R>(nt, npt) + (((sizeof(R) * (law ? 7 : 6) * (size_t)nt) + 15) & ~(size_t)15);
 }
-template <typename R> __host__ __device__ constexpr size_t res_lds_bytes(int nt, int mw, int mr,
+template <typename R> __host__ __device__ constexpr size_t res_off_walls(int nt, int npt, int law)
+{
+    return res_off_rc<R>(nt, npt, law) + 64;
+}
+template <typename R> __host__ __device__ constexpr size_t res_lds_bytes(int nt, int npt, int mw, int mr,
                                                                         bool ext, int law)
 {
-    return res_off_walls<R>(nt, law) + (sizeof(WallRec<R>) + (ext ? sizeof(RadRec) : 0)) * (size_t)mw +
-           sizeof(RoomRec) * (size_t)mr;
+    return res_off_walls<R>(nt, npt, law) +
+           (sizeof(WallRec<R>) + (ext ? sizeof(RadRec) : 0)) * (size_t)mw + sizeof(RoomRec) * (size_t)mr;
+}
+
+// FP32 level update with a compensated sum (Kahan): the level is the pair
+// hi + lo, and the step adds its increment to it, so that the rounding of
+// hi to FP32 is carried in lo instead of being lost.  Without it each step
+// rounds every node to the FP32 grid of its deviation (about 1e-6 K), and
+// where the state changes slowly those roundings repeat with the same sign
+// for thousands of steps; the wall's slowest modes (decay times of 1e4 s
+// and more) add them up to 1e-2 K over 1e5 steps.  The increment itself is
+// small, so its own FP32 error is far below the grid.
+template <typename R>
+__device__ __forceinline__ void comp_add(R hi, R lo, R inc, R &nhi, R &nlo)
+{
+    const R y = inc + lo;
+    const R s = hi + y;
+    nlo = y - (s - hi);
+    nhi = s;
 }
 
 // Keeps the scheduler from interleaving the nodes of a lane (bounds the
@@ -160,12 +183,16 @@ constexpr int kModePlain = 0;   // walls without zones or radiative sources
 constexpr int kModeZones = 1;   // zones coupled to walls
 constexpr int kModeExt = 2;     // radiative sources and / or linked zones
 
-template <typename R, int NPT, int NT, int MODE, int LAW> constexpr int res_waves_per_eu()
+__host__ __device__ constexpr int res_waves(int rbytes, int npt, int nt)
 {
-    if (NPT > 4) return 2;
+    if (npt > 4) return 2;
     // 512-lane workgroups keep four (three would leave room for only one
     // workgroup per CU)
-    return sizeof(R) == 8 && NT <= 256 ? 3 : 4;
+    return rbytes == 8 && nt <= 256 ? 3 : 4;
+}
+template <typename R, int NPT, int NT, int MODE, int LAW> constexpr int res_waves_per_eu()
+{
+    return res_waves((int)sizeof(R), NPT, NT);
 }
 
 // LAW: 0 = the shape law (scales x the launch's common shape factors),
@@ -190,8 +217,13 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                   "records keep 16-byte alignment");
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr int nthreads = NT;
-    constexpr size_t kRc = res_off_rc<R>(NT, LAW), kWalls = res_off_walls<R>(NT, LAW);
-    R *halo = (R *)lds;                                  // [4][NT]
+    constexpr size_t kRc = res_off_rc<R>(NT, NPT, LAW), kWalls = res_off_walls<R>(NT, NPT, LAW);
+    constexpr bool CMP = sizeof(R) == 4;                 // compensated FP32 levels
+    // low parts of the levels: [buffer][T, P][node of the lane][lane]; the
+    // buffers pair with the two register level buffers below
+    R *lo_a = (R *)lds;
+    R *lo_b = lo_a + 2 * NPT * NT;
+    R *halo = (R *)(lds + res_off_halo<R>(NT, NPT));    // [4][NT]
     R *facb = halo + 4 * NT;                             // [2][NT], [3][NT] under the Table 1 law
     double *s_rc = (double *)(lds + kRc);                // dt, Lv, rho_a, c_pa, c_pv, Pv_ref
     WallRec<R> *wr = (WallRec<R> *)(lds + kWalls);
@@ -357,6 +389,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             // deviations, where 0 is the wall's initial state)
             Ta_[q] = Tb_[q] = (R)(sizeof(R) == 8 && LAW == 0 ? 293.15 : 0.0);
             Pa_[q] = Pb_[q] = (R)(sizeof(R) == 8 && LAW == 0 ? 1000.0 : 0.0);
+            if constexpr (CMP) {
+                lo_a[q * NT + t] = lo_a[(NPT + q) * NT + t] = (R)0;
+                lo_b[q * NT + t] = lo_b[(NPT + q) * NT + t] = (R)0;
+            }
             info[q] = kFaceNone << 13;
             offs[q] = (uint32_t)((kWalls + offsetof(WallRec<R>, cc) + sizeof(R) * 4 * 3) >> 4) |
                       ((uint32_t)((kWalls + offsetof(WallRec<R>, fk) + sizeof(R) * 4 * kFaceNone) >> 4) << 16);
@@ -387,9 +423,10 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     if (amb_lane && wr[amb_slot].wroom >= 0 && wr[amb_slot].wside == amb_side) amb_zone = wr[amb_slot].wroom;
 
     // One DF step from (Tm, Pm) = level n-1 and (Tn, Pn) = level n; leaves
-    // level n+1 in (Tm, Pm).
+    // level n+1 in (Tm, Pm).  FP32: lm / ln hold the low parts of the same
+    // levels (lm is overwritten with those of level n+1).
     auto step = [&](R (&Tm)[NPT], R (&Pm)[NPT], const R (&Tn)[NPT], const R (&Pn)[NPT],
-                    const int64_t n) __attribute__((always_inline)) {
+                    R *lm, const R *ln, const int64_t n) __attribute__((always_inline)) {
         const int par = (int)(n & 1);
         // ---- A: publish halos, surface values and the ambient at t^n
         halo[t] = Tn[0];
@@ -403,8 +440,13 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 if (f & (3 << 8)) {
                     const int s = f & 0xff;
                     const int side = (f >> 8) & 1 ? 0 : 1;
-                    wr[s].surf[par][side][0] = wr[s].bc[side][6] + (double)Tn[q];
-                    wr[s].surf[par][side][1] = (double)wr[s].cc[0][3] + (double)Pn[q];
+                    double Ts = (double)Tn[q], Ps = (double)Pn[q];
+                    if constexpr (CMP) {
+                        Ts += (double)ln[q * NT + t];
+                        Ps += (double)ln[(NPT + q) * NT + t];
+                    }
+                    wr[s].surf[par][side][0] = wr[s].bc[side][6] + Ts;
+                    wr[s].surf[par][side][1] = (double)wr[s].cc[0][3] + Ps;
                 }
             }
         }
@@ -599,8 +641,25 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             const R Pl = q > 0 ? Pn[q > 0 ? q - 1 : 0] : Pl_nb;
             const R Tr = q + 1 < NPT ? Tn[q + 1 < NPT ? q + 1 : q] : Tr_nb;
             const R Pr = q + 1 < NPT ? Pn[q + 1 < NPT ? q + 1 : q] : Pr_nb;
-            R Tnew, Pnew;
-            if (!(f & (3 << 8))) {
+            R Tnew, Pnew, Tlo = 0, Plo = 0;
+            if (CMP && !(f & (3 << 8))) {
+                // FP32: the update as an increment of level n-1 (the same
+                // equations as below, minus (c + K) u^{n-1} on both sides),
+                // from differences to the neighbours of level n
+                const R KM = lM + kM[q];
+                const R KT = lT + kT[q];
+                const R dM = ccM + KM, dT = ccT + KT;
+                const R Tmq = Tm[q], Pmq = Pm[q];
+                const R dPr = Pr - Pmq, dPl = Pl - Pmq;
+                const R dP = div_nr<R>((R)2 * fma(kM[q], dPr, lM * dPl), dM);
+                // heat: 2 k_TM differences - (c_TM + K_TM) dP; under the shape
+                // law k_TM = b_TM k_M turns the first into b_TM dM dP
+                const R hX = LAW == 1 ? fma((R)2, fma(kXq, dPr, lX * dPl), -(ccX + lX + kXq) * dP)
+                                      : (bTM * ccM - ccX) * dP;
+                const R dTn = div_nr<R>(fma((R)2, fma(kT[q], Tr - Tmq, lT * (Tl - Tmq)), hX), dT);
+                comp_add<R>(Pmq, lm[(NPT + q) * NT + t], dP, Pnew, Plo);
+                comp_add<R>(Tmq, lm[q * NT + t], dTn, Tnew, Tlo);
+            } else if (!(f & (3 << 8))) {
                 const R KM = lM + kM[q];
                 const R KT = lT + kT[q];
                 const R SM = fma(kM[q], Pr, lM * Pl);
@@ -615,14 +674,14 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                     inv = rcp_nr(dM * dT);
                     Pnew = numM * (dT * inv);
                 } else {
-                    Pnew = div_nr(numM, dM);
+                    Pnew = div_nr<R>(numM, dM);
                 }
                 const R rhs = fma(ccT - KT, Tm[q],
                                   fma((R)2, fma(kT[q], Tr, lT * Tl),
                                       fma(ccX - KX, Pm[q],
                                           fma(-(ccX + KX), Pnew, (R)2 * SX))));
                 if constexpr (sizeof(R) == 8) Tnew = rhs * (dM * inv);
-                else Tnew = div_nr(rhs, dT);
+                else Tnew = div_nr<R>(rhs, dT);
             } else {
                 const int s = f & 0xff;
                 const int side = (f >> 8) & 1 ? 0 : 1;
@@ -648,25 +707,36 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                 const R gX = fma((R)2, k_X, (R)bc[5]);
                 const R dM = ccM + gM;
                 const R dT = ccT + gT;
-                const R numM = fma(ccM - gM, Pm[q], fma((R)4 * k_M, Pnb, (R)Bg));
-                R inv = 0;
-                if constexpr (sizeof(R) == 8) {
-                    inv = rcp_nr(dM * dT);
-                    Pnew = numM * (dT * inv);
+                double Tmf = (double)Tm[q], Pmf = (double)Pm[q];
+                if constexpr (CMP) {
+                    // increment form (as for the interior), with the exchange
+                    // with the air, 4 s (A - h u^{n-1}) over r
+                    const R Tlm = lm[q * NT + t], Plm = lm[(NPT + q) * NT + t];
+                    Tmf += (double)Tlm;
+                    Pmf += (double)Plm;
+                    const R EM = fma((R)-2 * (R)bc[4], Pm[q], (R)Bg);
+                    const R EQ = fma((R)-2 * (R)bc[0], Tm[q], fma((R)-2 * (R)bc[5], Pm[q], (R)Bq));
+                    const R dPs = Pnb - Pm[q];
+                    const R dP = div_nr<R>(fma((R)4 * k_M, dPs, EM), dM);
+                    const R dTn = div_nr<R>(fma((R)4 * k_T, Tnb - Tm[q],
+                                             fma((R)4 * k_X, dPs, fma(-(ccX + gX), dP, EQ))), dT);
+                    comp_add<R>(Pm[q], Plm, dP, Pnew, Plo);
+                    comp_add<R>(Tm[q], Tlm, dTn, Tnew, Tlo);
                 } else {
-                    Pnew = div_nr(numM, dM);
+                    const R numM = fma(ccM - gM, Pm[q], fma((R)4 * k_M, Pnb, (R)Bg));
+                    const R inv = rcp_nr(dM * dT);
+                    Pnew = numM * (dT * inv);
+                    const R rhs = fma(ccT - gT, Tm[q],
+                                  fma((R)4 * k_T, Tnb,
+                                  fma(ccX - gX, Pm[q],
+                                  fma(-(ccX + gX), Pnew,
+                                  fma((R)4 * k_X, Pnb, (R)Bq)))));
+                    Tnew = rhs * (dM * inv);
                 }
-                const R rhs = fma(ccT - gT, Tm[q],
-                              fma((R)4 * k_T, Tnb,
-                              fma(ccX - gX, Pm[q],
-                              fma(-(ccX + gX), Pnew,
-                              fma((R)4 * k_X, Pnb, (R)Bq)))));
-                if constexpr (sizeof(R) == 8) Tnew = rhs * (dM * inv);
-                else Tnew = div_nr(rhs, dT);
                 // applied flux (FP64) and its compensated integral
                 const double dt = s_rc[0];
-                const double Ts = 0.5 * ((double)Tnew + (double)Tm[q]);
-                const double Ps = 0.5 * ((double)Pnew + (double)Pm[q]);
+                const double Ts = 0.5 * ((double)Tnew + (double)Tlo + Tmf);
+                const double Ps = 0.5 * ((double)Pnew + (double)Plo + Pmf);
                 const double g = fma(-bc[2], Ps, Ag);
                 const double qh = fma(-bc[1], Ts, fma(-bc[3], Ps, Aq));
                 double *fw = X.flux;
@@ -677,9 +747,13 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
             }
             // padding nodes: the Table 1 law keeps them at zero (its faces
             // test for them); under the shape law they keep a physical state
-            if (LAW == 1 && !(f & (1 << 10))) { Tnew = 0; Pnew = 0; }
+            if (LAW == 1 && !(f & (1 << 10))) { Tnew = 0; Pnew = 0; Tlo = 0; Plo = 0; }
             Tm[q] = Tnew;   // level n-1 is no longer needed by node q
             Pm[q] = Pnew;
+            if constexpr (CMP) {
+                lm[q * NT + t] = Tlo;
+                lm[(NPT + q) * NT + t] = Plo;
+            }
             SCHED_FENCE();
         }
     };
@@ -688,18 +762,20 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     // step runs with the roles exchanged
     int i = 0;
     for (; i + 1 < ksteps; i += 2) {
-        step(Ta_, Pa_, Tb_, Pb_, n0 + i);
-        step(Tb_, Pb_, Ta_, Pa_, n0 + i + 1);
+        step(Ta_, Pa_, Tb_, Pb_, lo_a, lo_b, n0 + i);
+        step(Tb_, Pb_, Ta_, Pa_, lo_b, lo_a, n0 + i + 1);
     }
     if (i < ksteps) {
-        step(Ta_, Pa_, Tb_, Pb_, n0 + i);
+        step(Ta_, Pa_, Tb_, Pb_, lo_a, lo_b, n0 + i);
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
             R x = Ta_[q]; Ta_[q] = Tb_[q]; Tb_[q] = x;
             R y = Pa_[q]; Pa_[q] = Pb_[q]; Pb_[q] = y;
         }
     }
-    // now (Ta_, Pa_) = level n0+k-1 and (Tb_, Pb_) = level n0+k
+    // now (Ta_, Pa_) = level n0+k-1 and (Tb_, Pb_) = level n0+k; FP32 stores
+    // the high parts (the nearest FP32 values of the compensated levels), so
+    // a launch rounds to the storage grid once, at its end
 
     // ---- write back: level n0+k and n0+k-1, fluxes, zone air
     const ResIO O = *io;

@@ -398,9 +398,43 @@ void groups_of(const dfhm_ctx *c, std::vector<Group> &groups)
     for (int64_t r = 0; r < c->nr; ++r) groups[gid[find(r)]].rooms.push_back((int32_t)r);
 }
 
+// LDS of a resident workgroup of this context with mw walls and mr zones.
+size_t res_lds(const dfhm_ctx *c, int nt, int npt, int mw, int mr)
+{
+    const bool ext = c->extended;
+    const int law = c->cfg.law == DFHM_LAW_TABLE1;
+    return c->precision == DFHM_FP32 ? res_lds_bytes<float>(nt, npt, mw, mr, ext, law)
+                                     : res_lds_bytes<double>(nt, npt, mw, mr, ext, law);
+}
+
+// The LDS one workgroup may take so that LDS does not cut the number of
+// resident workgroups below what the register budget allows.  Every
+// workgroup of a launch gets the LDS of the launch's largest one (records for
+// its wall and zone counts), so one crowded workgroup would set the
+// occupancy of all: a batch with many small walls packs up to 54 walls into
+// a 2048-node workgroup, 84 KB of FP64 tables against the 80 KB that two
+// workgroups per CU leave.  Batches that do not fill every CU once are not
+// limited (their workgroups do not share CUs).
+size_t res_lds_budget(const dfhm_ctx *c, int nt, int npt)
+{
+    int dev = 0, ncu = 0, lds_cu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess || ncu <= 0 || lds_cu <= 0)
+        return SIZE_MAX;
+    if (c->N <= (int64_t)ncu * nt * npt) return SIZE_MAX;
+    const int waves = res_waves(c->precision == DFHM_FP32 ? 4 : 8, npt, nt);
+    const int wg_per_cu = std::max(1, waves * 4 / std::max(1, nt / 64));
+    return (size_t)lds_cu / (size_t)wg_per_cu;
+}
+
 dfhm_status pack(dfhm_ctx *c, int nt, int npt)
 {
     const int cap = nt * npt;
+    const size_t lds_budget = res_lds_budget(c, nt, npt);
+    int wcap = kResMaxWalls;   // walls per workgroup within the LDS budget
+    while (wcap > 1 && res_lds(c, nt, npt, wcap, 1) > lds_budget) --wcap;
     std::vector<Group> groups;
     groups_of(c, groups);
     std::vector<int> gsize(groups.size());
@@ -435,7 +469,8 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
         int chosen = -1;
         for (auto it = free_cap.lower_bound(need); it != free_cap.end(); ++it) {
             Bin &b = bins[it->second];
-            if (b.walls + gw <= kResMaxWalls && b.rooms + gr <= kResMaxRooms) {
+            if (b.walls + gw <= wcap && b.rooms + gr <= kResMaxRooms &&
+                (gr == 0 || res_lds(c, nt, npt, b.walls + gw, b.rooms + gr) <= lds_budget)) {
                 chosen = it->second;
                 free_cap.erase(it);
                 break;
@@ -450,7 +485,8 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
         b.walls += gw;
         b.rooms += gr;
         b.gs.push_back(g);
-        if (cap - b.used > 0) free_cap.emplace(cap - b.used, chosen);
+        // a bin at its wall limit takes nothing more (every group has a wall)
+        if (cap - b.used > 0 && b.walls < wcap) free_cap.emplace(cap - b.used, chosen);
     }
     std::vector<ResBlock> blocks(bins.size());
     std::vector<int32_t> bw, br;
@@ -575,7 +611,7 @@ void launch_res(dfhm_ctx *c, int k)
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT, MODE, LAW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)res_lds_bytes<R>(NT, kResMaxWalls, kResMaxRooms,
+                                  (int)res_lds_bytes<R>(NT, NPT, kResMaxWalls, kResMaxRooms,
                                                         MODE == kModeExt, LAW));
         attr_set = true;
     }
@@ -583,7 +619,7 @@ void launch_res(dfhm_ctx *c, int k)
     // this packing (at least one of each)
     const int mw = std::max(1, c->max_wpb), mr = std::max(1, c->max_rpb);
     hipLaunchKernelGGL((k_df_resident<R, NPT, NT, MODE, LAW>), dim3(c->n_blocks), dim3(NT),
-                       res_lds_bytes<R>(NT, mw, mr, MODE == kModeExt, LAW), c->stream, c->d_blocks,
+                       res_lds_bytes<R>(NT, NPT, mw, mr, MODE == kModeExt, LAW), c->stream, c->d_blocks,
                        c->d_block_walls,
                        c->d_block_rooms, c->d_walls, (const R *)c->d_T[0], (const R *)c->d_T[1],
                        (const R *)c->d_P[0], (const R *)c->d_P[1], c->d_lay, c->d_rooms,

@@ -2,7 +2,12 @@
 
 Error metric (per field, over all walls and nodes of the compared levels):
 max |x_gpu - x_ref| / max |x_ref|.  Bars: FP64 <= 1e-12, FP32 <= 1e-5 on T
-and on Pv separately.  Fluxes are compared relative to their largest value.
+and on Pv separately.  Every line also reports the stricter range-normalised
+error, max |x_gpu - x_ref| / (max x_ref - min x_ref) (T_rng, P_rng), which
+measures the error against the variation the run produced rather than
+against the absolute level (293 K, ~1 kPa); it is asserted for FP32 where the
+run produced a range of at least 1 K and 50 Pa.  Fluxes are compared
+relative to their largest value: FP64 <= 1e-11.
 """
 import math
 import sys
@@ -22,7 +27,7 @@ if not torch.cuda.is_available():
 from paper_1703_10119_amd import dfhm  # noqa: E402
 
 TOL = {dfhm.FP64: 1e-12, dfhm.FP32: 1e-5}
-FTOL = {dfhm.FP64: 1e-9, dfhm.FP32: 2e-4}
+FTOL = {dfhm.FP64: 1e-11, dfhm.FP32: 2e-4}
 SCHEDS = [("stream", dfhm.SCHED_STREAM), ("resident", dfhm.SCHED_RESIDENT)]
 PRECS = [("fp64", dfhm.FP64), ("fp32", dfhm.FP32)]
 
@@ -34,6 +39,11 @@ def say(msg):
 
 def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def rng(a, b):
+    """max |a - b| over the range of b (the range-normalised error)."""
+    return float(np.max(np.abs(a - b)) / max(float(np.max(b) - np.min(b)), 1e-300))
 
 
 def oracle_run(walls, cfg, steps, rooms=None, n0=None, levels=None):
@@ -51,7 +61,7 @@ def compare(s, ref, prec, what, check_prev=True):
     T, P = s.all_fields(0)
     Tr, Pr = ref.all_fields(0)
     eT, eP = rel(T, Tr), rel(P, Pr)
-    out = dict(T=eT, P=eP)
+    out = dict(T=eT, P=eP, T_rng=rng(T, Tr), P_rng=rng(P, Pr))
     if check_prev:
         T1, P1 = s.all_fields(1)
         Tr1, Pr1 = ref.all_fields(1)
@@ -63,6 +73,11 @@ def compare(s, ref, prec, what, check_prev=True):
     say(f"  {what}: " + " ".join(f"{k}={v:.2e}" for k, v in out.items()))
     tol, ftol = TOL[prec], FTOL[prec]
     assert eT <= tol and eP <= tol, out
+    if prec == dfhm.FP32:
+        if np.ptp(Tr) >= 1.0:
+            assert out["T_rng"] <= 1e-5, out
+        if np.ptp(Pr) >= 50.0:
+            assert out["P_rng"] <= 1e-5, out
     if check_prev:
         assert out["T1"] <= tol and out["P1"] <= tol, out
     assert out["flux_now"] <= ftol and out["flux_int"] <= ftol, out
@@ -82,6 +97,66 @@ def test_single_wall_full_day(pname, prec, sname, sched):
     s.sync()
     assert s.n == 86400
     compare(s, ref, prec, f"single {pname} {sname}")
+
+
+@pytest.mark.parametrize("pname,prec", PRECS)
+@pytest.mark.parametrize("sname,sched", SCHEDS)
+def test_building_at_dt60_over_30_days(pname, prec, sname, sched):
+    """The building batch at its largest time step, dt = 60 s, over its whole
+    30-day horizon (43,200 steps): 4 rooms x 6 walls (Nx capped by the
+    stability rule: 3-33 nodes), room air coupled every step."""
+    walls, rooms = wl.building_batch(4, seed=404, dt=60.0)
+    cfg = wl.default_config(dt=60.0)
+    say(f"building dt=60 s 30 days {pname} {sname}")
+    ref = oracle_run(walls, cfg, 43200, rooms)
+    s = dfhm.Solver(walls, cfg, rooms=rooms, precision=prec, schedule=sched)
+    s.step(43200)
+    s.sync()
+    compare(s, ref, prec, f"building dt60 30d {pname} {sname}")
+    Ta, Pa = s.rooms()
+    Tar, Par = ref.rooms()
+    eTa, ePa = rel(Ta, Tar), rel(Pa, Par)
+    say(f"  room air: T {eTa:.2e} P {ePa:.2e}")
+    assert eTa <= TOL[prec] and ePa <= TOL[prec]
+
+
+class _PerWall:
+    """The oracle run wall by wall in a pool of 16 threads (each wall is an
+    independent system without zones), gathered into the RefSim interface
+    that compare() reads."""
+
+    def __init__(self, walls, cfg, steps):
+        from concurrent.futures import ThreadPoolExecutor
+        W = len(walls["nx"])
+
+        def one(w):
+            r = oracle.RefSim(wl.subset(walls, [w]), cfg)
+            r.step(steps, threads=1)
+            return r
+        with ThreadPoolExecutor(16) as ex:
+            self.sims = list(ex.map(one, range(W)))
+
+    def all_fields(self, level=0):
+        f = [r.all_fields(level) for r in self.sims]
+        return np.concatenate([a for a, _ in f]), np.concatenate([b for _, b in f])
+
+    def fluxes(self):
+        f = [r.fluxes() for r in self.sims]
+        return np.concatenate([a for a, _ in f]), np.concatenate([b for _, b in f])
+
+
+def test_fp32_over_100000_steps_on_identical_grid_walls():
+    """FP32 resident path over the identical-grid batch's whole horizon:
+    32 walls sampled across the 65,536-wall batch (every 2048th), 1001
+    nodes, 100,000 steps of 1 s (27.8 h), against the FP64 oracle."""
+    walls = wl.subset(wl.uniform_batch(65536, seed=202, nx=1001), np.arange(0, 65536, 2048))
+    cfg = wl.default_config(dt=1.0)
+    say("identical grid sample fp32 100000 steps")
+    ref = _PerWall(walls, cfg, 100000)
+    s = dfhm.Solver(walls, cfg, precision=dfhm.FP32, schedule=dfhm.SCHED_RESIDENT)
+    s.step(100000)
+    s.sync()
+    compare(s, ref, dfhm.FP32, "identical grid fp32 100k steps")
 
 
 @pytest.mark.parametrize("pname,prec", PRECS)
@@ -407,10 +482,17 @@ def test_full_size_batch_sampled(pname, prec):
     ref = oracle_run(sub, cfg, steps)
     now, integ = s.fluxes()
     now_r, int_r = ref.fluxes()
+    got = [s.fields(w) for w in idx]
+    exp = [ref.fields(k) for k in range(len(idx))]
     for k, w in enumerate(idx):
-        T, P = s.fields(w)
-        Tr, Pr = ref.fields(k)
+        (T, P), (Tr, Pr) = got[k], exp[k]
         assert rel(T, Tr) <= TOL[prec] and rel(P, Pr) <= TOL[prec], (w, rel(T, Tr), rel(P, Pr))
+    T, P = (np.concatenate([g[i] for g in got]) for i in (0, 1))
+    Tr, Pr = (np.concatenate([e[i] for e in exp]) for i in (0, 1))
+    say(f"  sampled walls: T={rel(T, Tr):.2e} P={rel(P, Pr):.2e} T_rng={rng(T, Tr):.2e} "
+        f"P_rng={rng(P, Pr):.2e} flux_int={rel(integ[idx], int_r):.2e}")
+    if prec == dfhm.FP32 and np.ptp(Pr) >= 50.0:
+        assert rng(P, Pr) <= 1e-5
     assert rel(integ[idx], int_r) <= FTOL[prec]
     s.close()
 
