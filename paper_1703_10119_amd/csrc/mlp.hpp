@@ -15,17 +15,65 @@ namespace dfhm {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// FP32 -> BF16, round to nearest even (gfx950 converts in hardware:
+// v_cvt_pk_bf16_f32, two values per instruction)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t f2bf2(float a, float b)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0;   // NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// GELU and its derivative (erf form).
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU z Phi(z), Phi the standard normal CDF, with Phi(-|z|) = erfc(|z|/sqrt 2) / 2
+// from the rational-exponential approximation of Abramowitz & Stegun 7.1.26
+// (Hastings): erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
+// t = 1 / (1 + p x), x >= 0, absolute error below 1.5e-7.  So the GELU
+// error is below 7.5e-8 |z| plus FP32 rounding, at one reciprocal and one
+// base-2 exponential (the library erff costs about three times as many
+// instructions in the GEMM epilogues).
+__device__ __forceinline__ float gelu(float z)
+{
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
+    // h = Phi(-|z|): the coefficients are a_i / 2, and exp(-z^2 / 2) = 2^(-z^2 / (2 ln 2))
+    const float p = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 0.5307027145f, -0.7265760135f), 0.7107068705f),
+                                     -0.142248368f), 0.127414796f);
+    const float h = p * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
+    // z (1 - h) for z >= 0 and z h below: max(z, 0) - |z| h
+    return fmaf(-az, h, fmaxf(z, 0.f));
+}
+// The same GELU on four values, written step by step across them so that
+// four independent chains interleave (same operations per value, so the
+// results equal gelu()'s bit for bit).
+__device__ __forceinline__ f32x4 gelu4(f32x4 z)
+{
+    f32x4 az, t, p, e, r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        az[q] = fabsf(z[q]);
+        t[q] = fmaf(0.3275911f * 0.70710678118654752f, az[q], 1.0f);
+        e[q] = -0.72134752044448170f * z[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        t[q] = __builtin_amdgcn_rcpf(t[q]);
+        e[q] = __builtin_amdgcn_exp2f(e[q] * z[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = fmaf(t[q], 0.5307027145f, -0.7265760135f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = fmaf(t[q], p[q], 0.7107068705f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = fmaf(t[q], p[q], -0.142248368f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = fmaf(t[q], p[q], 0.127414796f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = fmaf(-az[q], (t[q] * p[q]) * e[q], fmaxf(z[q], 0.f));
+    return r;
+}
+// Its derivative (erf form, library erff).
 __device__ __forceinline__ float gelu_d(float z)
 {
     const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
@@ -42,8 +90,8 @@ enum { OP_K = 0, OP_MN = 1 };
 // Epilogues.
 enum {
     EPI_F32 = 0,        // Cf[z][m][n] = acc (split-K partials when gridDim.z > 1)
-    EPI_BIAS_F32 = 1,   // Cf[m][n] = acc + bias[n]
-    EPI_BIAS_GELU = 2,  // z = acc + bias[n]: Cb[m][n] = bf16(gelu(z)) and, when pre
+    EPI_BIAS_F32 = 1,   // Cf[m][n] = bias[n] + acc (the sum starts at the bias)
+    EPI_BIAS_GELU = 2,  // z = bias[n] + acc: Cb[m][n] = bf16(gelu(z)) and, when pre
                         // is not null, pre[m][n] = bf16(z) (kept for the backward pass)
     EPI_GELU_BWD = 3    // Cb[m][n] = bf16(acc * gelu'(aux[m][n]))
 };
@@ -126,14 +174,19 @@ k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
 
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-
     const int fr = lane & 15;          // row (A) / column (B) inside a 16 x 16 tile
     const int fk = (lane >> 4) * 8;    // this lane's 8 reduction indices
+
+    // the bias epilogues start the sums at the bias (the fused inference
+    // kernel does the same, so both round alike)
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = n0 + wn * 64 + j * 16 + fr;
+        const float b0 = ((EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_GELU) && col < N) ? bias[col] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = (f32x4){b0, b0, b0, b0};
+    }
     if (kbeg < kend) {
         TileRegs ra = fetch_tile<LA>(A, lda, m0, M, kbeg, kend, tid);
         TileRegs rb = fetch_tile<LB>(B, ldb, n0, N, kbeg, kend, tid);
@@ -182,15 +235,231 @@ k_gemm_bf16(int M, int N, int K, const uint16_t *__restrict__ A, int lda,
                 if (EPI == EPI_F32) {
                     Cf[(int64_t)blockIdx.z * M * ldc + o] = v;
                 } else if (EPI == EPI_BIAS_F32) {
-                    Cf[o] = v + bias[col];
+                    Cf[o] = v;
                 } else if (EPI == EPI_BIAS_GELU) {
-                    const float z = v + bias[col];
+                    const float z = v;
                     if (pre) pre[(int64_t)row * N + col] = f2bf(z);
-                    Cb[o] = f2bf(gelu(z));
+                    Cb[o] = f2bf(gelu(z));   // the fused inference kernel's arithmetic
                 } else {
                     Cb[o] = f2bf(v * gelu_d(bf2f(aux[o])));
                 }
             }
+}
+
+// ---------------------------------------------------------------- inference
+// Weights in MFMA fragment order, for the inference kernel: a layer W[N][K]
+// (N a multiple of 16) becomes tiles of 16 outputs x 32 inputs, each 1 KB
+// in the order the 64 lanes of a wave read it as the A operand of
+// v_mfma_f32_16x16x32_bf16 -- lane l takes outputs n = 16 nt + (l & 15) and
+// inputs 32 ks + 8 (l >> 4) .. +7 -- so that a wave loads a fragment as one
+// contiguous, fully used kilobyte:
+//   ws[((nt KS + ks) 64 + l) 8 + e] = bf16(W[16 nt + (l & 15)][32 ks + 8 (l >> 4) + e]),
+// KS = ceil(K / 32), zero for inputs at or beyond K and outputs at or
+// beyond N (the copy holds ceil(N / 16) tiles).
+__global__ void k_pack_swizzled(const float *__restrict__ w, uint16_t *__restrict__ ws, int N, int K)
+{
+    const int KS = (K + 31) / 32, NT = (N + 15) / 16;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)NT * KS * 512) return;
+    const int e = (int)(i & 7), l = (int)((i >> 3) & 63);
+    const int64_t t = i >> 9;
+    const int ks = (int)(t % KS), nt = (int)(t / KS);
+    const int n = nt * 16 + (l & 15), k = ks * 32 + (l >> 4) * 8 + e;
+    ws[i] = (k < K && n < N) ? f2bf(w[(int64_t)n * K + k]) : (uint16_t)0;
+}
+
+// The whole forward pass of a block of 128 samples in one workgroup of 8
+// waves: the hidden activations stay in LDS from layer to layer (BF16,
+// [128][width + FI_PAD]), the weights stream from L2 into registers as MFMA
+// operands (fragment order, above), and only the input rows and the output
+// layer touch memory.  Each layer computes out^T = W act^T, so that a lane's
+// four accumulators are four consecutive outputs of one sample (one 8-byte
+// LDS store of BF16 GELU values, or one 16-byte store of FP32 outputs).
+// Wave w owns output columns [16 NJ w, 16 NJ (w+1)) of every hidden layer
+// (width = 128 NJ) for all 128 samples, and samples [16 w, 16 w + 16) of
+// the output layer.  The arithmetic per element is that of the
+// layer-by-layer path (k_gemm_bf16): the sum starts at the bias, FP32 MFMA
+// accumulation over K in steps of 32 in ascending order, GELU, BF16
+// rounding -- so the two paths agree bit for bit.
+constexpr int FI_M = 128, FI_NW = 8, FI_PAD = 8, FI_KC = 64;
+
+// Layer operands by base and stride (no per-layer pointer table, which the
+// kernel would have to copy to scratch memory to index), weights in
+// fragment order: layer 0 W0 (K = n_in), b0; hidden layer l = 1 .. depth-1
+// at Wh + (l-1) wh_stride, bh + (l-1) bh_stride; the output layer Wo
+// (n_outp outputs), bo.
+struct FusedNet {
+    const uint16_t *W0, *Wh, *Wo;
+    const float *b0, *bh, *bo;
+    int64_t wh_stride, bh_stride;
+    int depth;       // hidden layers
+    int n_in;        // inputs (multiple of 8), x row stride ldx >= n_in
+    int n_outp;      // output columns written (multiple of 16, <= 32)
+};
+
+template <int NJ>
+__host__ __device__ constexpr size_t fused_lds_bytes()
+{
+    const size_t act = (size_t)FI_M * (128 * NJ + FI_PAD) * 2;
+    const size_t stage = 2 * (size_t)FI_M * (FI_KC + FI_PAD) * 2;
+    return act > stage ? act : stage;
+}
+
+template <int NJ>
+__global__ void __launch_bounds__(64 * FI_NW) __attribute__((amdgpu_waves_per_eu(2)))
+k_mlp_infer_fused(FusedNet net, const uint16_t *__restrict__ x, int ldx, int64_t batch,
+                  float *__restrict__ y, int ldy)
+{
+    extern __shared__ __align__(16) uint16_t lds_act[];
+    constexpr int W = 128 * NJ;                    // width
+    constexpr int KSW = W / 32;                    // K steps of a hidden layer
+    constexpr int LDA = W + FI_PAD;
+    constexpr int LDS_ = FI_KC + FI_PAD;           // staging row stride
+    constexpr int NT = 64 * FI_NW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * FI_M;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const int nw0 = wave * NJ * 16;                // first output column of this wave
+    const int nl = (lane >> 4) * 4;                // lane's first column in a 16-column tile
+    const uint4 z4 = make_uint4(0, 0, 0, 0);
+
+    f32x4 acc[8][NJ];
+    // sums start at the bias of the lane's four columns
+    auto init = [&](const float *__restrict__ bias) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const float4 bb = *(const float4 *)(bias + nw0 + j * 16 + nl);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i][j] = (f32x4){bb.x, bb.y, bb.z, bb.w};
+        }
+    };
+    // fragment (wave's column tile j, K step ks) of a layer with KS K steps
+    auto wfrag = [&](const uint16_t *__restrict__ Wl, int KS, int j, int ks) {
+        return __builtin_bit_cast(
+            bf16x8, *(const uint4 *)(Wl + (((size_t)(nw0 / 16 + j) * KS + ks) * 64 + lane) * 8));
+    };
+    // GELU and BF16 of the accumulators into the activation block
+    auto hidden_out = [&]() {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const f32x4 g = gelu4(acc[i][j]);
+                uint2 v;
+                v.x = f2bf2(g[0], g[1]);
+                v.y = f2bf2(g[2], g[3]);
+                *(uint2 *)&lds_act[(i * 16 + fr) * LDA + nw0 + j * 16 + nl] = v;
+            }
+    };
+
+    // ---- layer 0: input rows from x, staged through LDS in chunks of FI_KC
+    // (128 rows x 8 pieces of 16 B per chunk, two per lane)
+    {
+        const int K = net.n_in, KS = (K + 31) / 32;
+        const uint16_t *__restrict__ Wl = net.W0;
+        uint16_t *stage = lds_act;
+        auto fetch = [&](int k0, uint4 (&r)[2]) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int pc = tid + q * NT, row = pc >> 3, kc = (pc & 7) * 8;
+                const int64_t g = m0 + row;
+                r[q] = z4;
+                if (g < batch && k0 + kc < K) r[q] = *(const uint4 *)(x + g * ldx + k0 + kc);
+            }
+        };
+        auto put = [&](int buf, const uint4 (&r)[2]) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int pc = tid + q * NT, row = pc >> 3, kc = (pc & 7) * 8;
+                *(uint4 *)(stage + (size_t)buf * FI_M * LDS_ + row * LDS_ + kc) = r[q];
+            }
+        };
+        init(net.b0);
+        uint4 rg[2];
+        fetch(0, rg);
+        put(0, rg);
+        __syncthreads();
+        int buf = 0;
+        for (int k0 = 0; k0 < K; k0 += FI_KC) {
+            const bool more = k0 + FI_KC < K;
+            if (more) fetch(k0 + FI_KC, rg);
+#pragma unroll
+            for (int kk = 0; kk < FI_KC; kk += 32) {
+                const int ks = (k0 + kk) / 32;
+                if (ks < KS) {
+                    bf16x8 wf[NJ];
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) wf[j] = wfrag(Wl, KS, j, ks);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const bf16x8 af = *(const bf16x8 *)(stage + (size_t)buf * FI_M * LDS_ +
+                                                            (i * 16 + fr) * LDS_ + kk + fk);
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af, acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+            if (more) put(buf ^ 1, rg);   // last read before the previous barrier
+            __syncthreads();
+            buf ^= 1;
+        }
+        hidden_out();
+        __syncthreads();
+    }
+    // ---- hidden layers 1 .. depth-1: B operand from the activation block
+    for (int l = 1; l < net.depth; ++l) {
+        const uint16_t *__restrict__ Wl = net.Wh + (l - 1) * net.wh_stride;
+        init(net.bh + (l - 1) * net.bh_stride);
+        bf16x8 wf[NJ], wn[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) wf[j] = wfrag(Wl, KSW, j, 0);
+#pragma unroll 2
+        for (int ks = 0; ks < KSW; ++ks) {
+            if (ks + 1 < KSW) {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) wn[j] = wfrag(Wl, KSW, j, ks + 1);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const bf16x8 af = *(const bf16x8 *)(lds_act + (i * 16 + fr) * LDA + ks * 32 + fk);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af, acc[i][j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) wf[j] = wn[j];
+        }
+        __syncthreads();          // every wave has read the layer's input
+        hidden_out();
+        __syncthreads();
+    }
+    // ---- output layer: wave w takes samples [16 w, 16 w + 16), all outputs
+    {
+        const int no = net.n_outp >> 4;
+        f32x4 o[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float4 bb = j < no ? *(const float4 *)(net.bo + j * 16 + nl) : make_float4(0.f, 0.f, 0.f, 0.f);
+            o[j] = (f32x4){bb.x, bb.y, bb.z, bb.w};
+        }
+        for (int ks = 0; ks < KSW; ++ks) {
+            const bf16x8 af = *(const bf16x8 *)(lds_act + (wave * 16 + fr) * LDA + ks * 32 + fk);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                if (j < no) {
+                    const bf16x8 wf = __builtin_bit_cast(
+                        bf16x8, *(const uint4 *)(net.Wo + (((size_t)j * KSW + ks) * 64 + lane) * 8));
+                    o[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf, af, o[j], 0, 0, 0);
+                }
+        }
+        const int64_t row = m0 + wave * 16 + fr;
+        if (row < batch) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                if (j < no) *(float4 *)(y + row * ldy + j * 16 + nl) = make_float4(o[j][0], o[j][1], o[j][2], o[j][3]);
+        }
+    }
 }
 
 // Sum of split-K partials: out[i] = sum_z part[z][i] (+ out[i] if accumulate).
@@ -280,18 +549,14 @@ __global__ void k_adamw(float *__restrict__ w, float *__restrict__ m, float *__r
     w[i] = wi;
 }
 
-// BF16 copy of a weight matrix w[N][K] (FP32) as wb[N][ld]; with dup the row
-// is stored twice, wb[n][k] = wb[n][K + k], the weight operand of a layer
-// whose input is a BF16 pair (hi | lo).
+// BF16 copy of a weight matrix w[N][K] (FP32) as wb[N][ld].
 __global__ void k_pack_weights(const float *__restrict__ w, uint16_t *__restrict__ wb, int N, int K,
-                               int ld, int dup)
+                               int ld)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)N * K) return;
     const int64_t n = i / K, k = i % K;
-    const uint16_t h = f2bf(w[i]);
-    wb[n * ld + k] = h;
-    if (dup) wb[n * ld + K + k] = h;
+    wb[n * ld + k] = f2bf(w[i]);
 }
 
 // Features of one sample: the outdoor temperature and humidity of side 0

@@ -24,6 +24,7 @@ struct Layer {
     int K, N, Np;             // inputs, logical outputs, padded outputs
     size_t w_off, b_off;      // offsets into the flat FP32 parameter buffer
     size_t wb_off;            // offset of the BF16 weight operand [Np][K]
+    size_t ws_off;            // offset of the same in fragment order (k_pack_swizzled)
 };
 
 // Scratch of dfhm_mlp_infer_noalloc: two hidden-activation buffers used in
@@ -64,11 +65,13 @@ struct dfhm_mlp {
     int64_t n_params = 0;      // logical parameters (exposed)
     int64_t n_dev = 0;         // device parameters (with padding)
     int64_t n_wb = 0;          // BF16 weight operands
+    int64_t n_ws = 0;          // BF16 weight operands in fragment order
     int device = 0;            // device the network lives on
     void *scratch = nullptr;   // that device's address of `scratch` (nullptr: not available)
     std::string scratch_msg;   // why it is not
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     uint16_t *wb = nullptr;
+    uint16_t *ws = nullptr;    // fragment-order copies (inference kernel)
     uint8_t *mask = nullptr;
     std::vector<uint16_t *> act;   // act[0] = input (caller's), act[l+1] = output of layer l [B][N]
     std::vector<uint16_t *> pre;   // pre-activations of hidden layers
@@ -96,6 +99,9 @@ dfhm_status mfail(dfhm_mlp *m, dfhm_status s, const std::string &msg)
         if (e_ != hipSuccess)                                                                \
             return mfail((mm), DFHM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// elements of a layer's fragment-order copy: ceil(Np / 16) x ceil(K / 32) tiles of 512
+int64_t swizzled_size(const Layer &ly) { return (int64_t)((ly.Np + 15) / 16) * ((ly.K + 31) / 32) * 512; }
 
 template <typename T>
 dfhm_status dalloc(dfhm_mlp *m, T **p, size_t n)
@@ -137,6 +143,57 @@ void forward_into(dfhm_mlp *m, int batch, In in, Out out, Pre pre, float *y)
         else
             gemm<OP_K, OP_K, EPI_BIAS_F32>(m, batch, ly.Np, ly.K, in(l), ly.K, W, ly.K, y,
                                            nullptr, ly.Np, b, nullptr, nullptr, 1);
+    }
+}
+
+// Whether the fused inference kernel covers this network: width a multiple
+// of 128 up to 512 (8 waves x width / 8 columns), outputs within two tiles.
+bool fused_ok(const dfhm_mlp *m)
+{
+    const int w = m->cfg.width;
+    return w % 128 == 0 && w <= 512 && m->cfg.n_out <= 32;
+}
+
+template <int NJ>
+void launch_fused(dfhm_mlp *m, const FusedNet &net, const uint16_t *x, int64_t batch, float *y)
+{
+    static bool attr_set = false;   // above the default 64 KB of LDS
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_mlp_infer_fused<NJ>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes<NJ>());
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_mlp_infer_fused<NJ>, dim3((unsigned)((batch + FI_M - 1) / FI_M)),
+                       dim3(64 * FI_NW), fused_lds_bytes<NJ>(), m->stream, net, x, m->cfg.n_in, batch,
+                       y, kOutPad);
+}
+
+// Forward pass of inference in one launch (fused_ok): outputs y [batch][kOutPad]
+// FP32 (the first 16 or 32 columns written).
+void forward_fused(dfhm_mlp *m, const uint16_t *x, int64_t batch, float *y)
+{
+    FusedNet net{};
+    const int L = (int)m->layers.size();
+    const Layer &l0 = m->layers[0], &lo = m->layers[L - 1];
+    net.W0 = m->ws + l0.ws_off;
+    net.b0 = m->w + l0.b_off;
+    net.Wo = m->ws + lo.ws_off;
+    net.bo = m->w + lo.b_off;
+    if (L > 2) {
+        // hidden layers are equal in size, so they sit at a fixed stride
+        net.Wh = m->ws + m->layers[1].ws_off;
+        net.bh = m->w + m->layers[1].b_off;
+        net.wh_stride = L > 3 ? (int64_t)(m->layers[2].ws_off - m->layers[1].ws_off) : 0;
+        net.bh_stride = L > 3 ? (int64_t)(m->layers[2].b_off - m->layers[1].b_off) : 0;
+    }
+    net.depth = L - 1;
+    net.n_in = m->cfg.n_in;
+    net.n_outp = (m->cfg.n_out + 15) / 16 * 16;
+    switch (m->cfg.width / 128) {
+    case 1: launch_fused<1>(m, net, x, batch, y); break;
+    case 2: launch_fused<2>(m, net, x, batch, y); break;
+    case 3: launch_fused<3>(m, net, x, batch, y); break;
+    default: launch_fused<4>(m, net, x, batch, y); break;
     }
 }
 
@@ -234,8 +291,13 @@ void to_device(const dfhm_mlp *m, const float *in, std::vector<float> &dev)
 void pack_weights(dfhm_mlp *m)
 {
     for (const Layer &ly : m->layers)
+    {
         hipLaunchKernelGGL(k_pack_weights, dim3(blocks_of((int64_t)ly.Np * ly.K, 256)), dim3(256), 0,
-                           m->stream, m->w + ly.w_off, m->wb + ly.wb_off, ly.Np, ly.K, ly.K, 0);
+                           m->stream, m->w + ly.w_off, m->wb + ly.wb_off, ly.Np, ly.K, ly.K);
+        if (m->ws)
+            hipLaunchKernelGGL(k_pack_swizzled, dim3(blocks_of(swizzled_size(ly), 256)),
+                               dim3(256), 0, m->stream, m->w + ly.w_off, m->ws + ly.ws_off, ly.Np, ly.K);
+    }
 }
 
 dfhm_status upload(dfhm_mlp *m, const std::vector<float> &dev)
@@ -265,7 +327,7 @@ dfhm_status dfhm_mlp_create(const dfhm_mlp_config *cfg, dfhm_mlp **out)
     m->stream = (hipStream_t)cfg->stream;
     if (hipGetDevice(&m->device) != hipSuccess) { delete m; return DFHM_E_DEVICE; }
     m->scratch = scratch_on(m->device, m->scratch_msg);
-    size_t o = 0, ob = 0;
+    size_t o = 0, ob = 0, os = 0;
     int K = cfg->n_in;
     for (int l = 0; l <= cfg->depth; ++l) {
         Layer ly;
@@ -275,16 +337,18 @@ dfhm_status dfhm_mlp_create(const dfhm_mlp_config *cfg, dfhm_mlp **out)
         ly.w_off = o; o += (size_t)ly.Np * ly.K;
         ly.b_off = o; o += (size_t)ly.Np;
         ly.wb_off = ob; ob += (size_t)ly.Np * ly.K;
+        ly.ws_off = os; os += (size_t)swizzled_size(ly);
         m->n_params += (int64_t)ly.N * ly.K + ly.N;
         m->layers.push_back(ly);
         K = ly.N;
     }
     m->n_dev = (int64_t)o;
     m->n_wb = (int64_t)ob;
+    m->n_ws = (int64_t)os;
     const int B = cfg->max_batch, L = (int)m->layers.size();
     auto bail = [&](dfhm_status s) { dfhm_mlp_destroy(m); return s; };
     if (dalloc(m, &m->w, o) || dalloc(m, &m->m, o) || dalloc(m, &m->v, o) || dalloc(m, &m->g, o) ||
-        dalloc(m, &m->wb, ob) || dalloc(m, &m->mask, o) || dalloc(m, &m->out, (size_t)B * kOutPad) ||
+        dalloc(m, &m->wb, ob) || dalloc(m, &m->ws, os) || dalloc(m, &m->mask, o) || dalloc(m, &m->out, (size_t)B * kOutPad) ||
         dalloc(m, &m->loss_part, (size_t)(B + 255) / 256))
         return bail(DFHM_E_NOMEM);
     m->act.assign(L + 1, nullptr);
@@ -494,7 +558,8 @@ dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, co
     dfhm_status st = infer_args(m, x_dev, batch, scale, flux_dev, err_est_dev);
     if (st) return st;
     if (batch > m->cfg.max_batch) return mfail(m, DFHM_E_INVAL, "batch above max_batch");
-    forward(m, x_dev, (int)batch);
+    if (fused_ok(m)) forward_fused(m, x_dev, batch, m->out);
+    else forward(m, x_dev, (int)batch);
     MHIP(m, hipGetLastError());
     return infer_decode(m, m->out, batch, scale, flux_dev, err_est_dev);
 }
@@ -502,7 +567,9 @@ dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, co
 int64_t dfhm_mlp_noalloc_max_batch(const dfhm_mlp *m)
 {
     if (!m) return -1;
-    const size_t per_row = 2 * (size_t)m->cfg.width * sizeof(uint16_t) + kOutPad * sizeof(float);
+    // the fused kernel keeps the hidden activations on chip: only the outputs
+    const size_t per_row = (fused_ok(m) ? 0 : 2 * (size_t)m->cfg.width * sizeof(uint16_t)) +
+                           kOutPad * sizeof(float);
     return (int64_t)((kScratchBytes - 1024) / per_row);
 }
 
@@ -515,6 +582,14 @@ dfhm_status dfhm_mlp_infer_noalloc(dfhm_mlp *m, const uint16_t *x_dev, int64_t b
         return mfail(m, DFHM_E_INVAL, "batch above the allocation-free limit (" +
                                           std::to_string(dfhm_mlp_noalloc_max_batch(m)) + " rows)");
     if (!m->scratch) return mfail(m, DFHM_E_DEVICE, "scratch not available: " + m->scratch_msg);
+    if (fused_ok(m)) {
+        // the outputs only, at the start of the array; every element the
+        // decode reads is written by this call's forward pass
+        float *y = (float *)m->scratch;
+        forward_fused(m, x_dev, batch, y);
+        MHIP(m, hipGetLastError());
+        return infer_decode(m, y, batch, scale, flux_dev, err_est_dev);
+    }
     // [hidden A][hidden B][output], each 256-byte aligned; every element a
     // kernel reads was written earlier in this call, so nothing is cleared
     const size_t hid = ((size_t)batch * m->cfg.width * sizeof(uint16_t) + 255) / 256 * 256;

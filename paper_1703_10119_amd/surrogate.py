@@ -525,10 +525,13 @@ def kernel_bench(batch=65536, train_batch=16384, iters=50, seed=0):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3 / n
 
+    scale = np.array([0.0, 1.0, 0.0, 1.0, 0.0, 1.0, 0.0, 1.0], np.float32)
+    t_inf = timed(lambda: net.infer(x, scale), iters)
     t_fwd = timed(lambda: net.forward(x), iters)
     t_train = timed(lambda: net.train_step(xt, yt, 1e-4), iters)
     net.close()
-    return dict(forward_s=t_fwd, forward_tflops=fwd_flops * batch / t_fwd / 1e12,
+    return dict(infer_s=t_inf, infer_tflops=fwd_flops * batch / t_inf / 1e12,
+                forward_s=t_fwd, forward_tflops=fwd_flops * batch / t_fwd / 1e12,
                 train_step_s=t_train,
                 train_tflops=3.0 * fwd_flops * train_batch / t_train / 1e12,
                 batch=batch, train_batch=train_batch, flops_per_sample=fwd_flops)
