@@ -418,12 +418,26 @@ dfhm_status dfhm_mlp_decode_ensemble(const float *const *y_dev, int32_t n_nets, 
 dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, const float *scale,
                            float *flux_dev, float *err_est_dev);
 
+/* dfhm_mlp_infer over an ensemble of 1 to 4 networks with the same inputs
+ * (n_in), stream and device: every member's forward pass on x_dev, then the
+ * ensemble decode (as dfhm_mlp_decode_ensemble): flux_dev[b][f] the mean of
+ * the members' fluxes, err_est_dev[b] the maximum over the two fields of the
+ * mean of their error estimates.  Device pointers, queued on the members'
+ * stream.  DFHM_E_INVAL for a null member, members that differ, n_nets
+ * outside [1, 4], and as dfhm_mlp_infer for each member; the message goes
+ * to the first member's dfhm_mlp_last_error. */
+dfhm_status dfhm_mlp_infer_ensemble(dfhm_mlp *const *nets, int32_t n_nets, const uint16_t *x_dev,
+                                    int64_t batch, const float *scale, float *flux_dev,
+                                    float *err_est_dev);
+
 /* dfhm_mlp_infer for callers that cannot allocate device memory (code under
- * HIP graph capture, tight serving loops): the same results, with the hidden
- * activations and the raw outputs in one statically allocated 64 MiB device
+ * HIP graph capture, tight serving loops): the same results, with the raw
+ * outputs (and, for a network the one-launch inference kernel does not
+ * cover, the hidden activations) in one statically allocated 64 MiB device
  * array per GPU instead of the network's buffers; it calls no allocator.
- * batch may not exceed dfhm_mlp_noalloc_max_batch(m) (30,840 rows at width
- * 512; DFHM_E_INVAL above it).  Calls on one GPU share that array: two calls
+ * batch may not exceed dfhm_mlp_noalloc_max_batch(m) (DFHM_E_INVAL above it):
+ * 524,280 rows at width 256 or 512, (64 MiB - 1 KiB) / (4 width + 128) at
+ * other widths.  Calls on one GPU share that array: two calls
  * whose work overlaps on one GPU (different streams, or threads) race, and
  * the caller must order them.  Errors as dfhm_mlp_infer, and DFHM_E_DEVICE
  * if the array's address could not be resolved when the network was

@@ -564,6 +564,36 @@ dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, co
     return infer_decode(m, m->out, batch, scale, flux_dev, err_est_dev);
 }
 
+dfhm_status dfhm_mlp_infer_ensemble(dfhm_mlp *const *nets, int32_t n_nets, const uint16_t *x_dev,
+                                    int64_t batch, const float *scale, float *flux_dev,
+                                    float *err_est_dev)
+{
+    if (!nets || n_nets < 1 || n_nets > kMaxEnsemble || !nets[0]) return DFHM_E_INVAL;
+    dfhm_mlp *m0 = nets[0];
+    DecodeNets dn{};
+    for (int k = 0; k < n_nets; ++k) {
+        dfhm_mlp *m = nets[k];
+        if (!m) return mfail(m0, DFHM_E_INVAL, "null ensemble member");
+        dfhm_status st = infer_args(m, x_dev, batch, scale, flux_dev, err_est_dev);
+        if (st) return mfail(m0, st, "member " + std::to_string(k) + ": " + m->err);
+        if (batch > m->cfg.max_batch) return mfail(m0, DFHM_E_INVAL, "batch above a member's max_batch");
+        if (m->cfg.n_in != m0->cfg.n_in || m->stream != m0->stream || m->device != m0->device)
+            return mfail(m0, DFHM_E_INVAL, "ensemble members differ in inputs, stream or device");
+    }
+    for (int k = 0; k < n_nets; ++k) {
+        dfhm_mlp *m = nets[k];
+        if (fused_ok(m)) forward_fused(m, x_dev, batch, m->out);
+        else forward(m, x_dev, (int)batch);
+        MHIP(m0, hipGetLastError());
+        dn.y[k] = m->out;
+    }
+    dn.n = n_nets;
+    dn.ld = kOutPad;
+    dfhm_status st = decode_nets(dn, batch, scale, 1.0f, flux_dev, err_est_dev, nullptr, m0->stream);
+    if (st) return mfail(m0, st, "decode launch failed");
+    return DFHM_OK;
+}
+
 int64_t dfhm_mlp_noalloc_max_batch(const dfhm_mlp *m)
 {
     if (!m) return -1;

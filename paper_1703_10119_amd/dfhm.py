@@ -117,6 +117,7 @@ EXPORTS = ("dfhm_arena_bytes", "dfhm_create", "dfhm_room_couple", "dfhm_zone_lin
            "dfhm_mlp_train_step", "dfhm_mlp_last_error", "dfhm_mlp_destroy",
            "dfhm_mlp_features", "dfhm_mlp_decode", "dfhm_mlp_decode_ensemble",
            "dfhm_mlp_get_intermediate", "dfhm_mlp_infer", "dfhm_mlp_infer_noalloc",
+           "dfhm_mlp_infer_ensemble",
            "dfhm_mlp_noalloc_max_batch")
 
 _lib = None
@@ -198,6 +199,8 @@ def load(path: str = LIB_PATH):
               L.dfhm_mlp_features, L.dfhm_mlp_decode, L.dfhm_mlp_decode_ensemble,
               L.dfhm_mlp_infer, L.dfhm_mlp_get_intermediate):
         f.restype = C.c_int
+    L.dfhm_mlp_infer_ensemble.argtypes = [P, I32, P, I64, P, P, P]
+    L.dfhm_mlp_infer_ensemble.restype = C.c_int
     L.dfhm_mlp_infer_noalloc.argtypes = [P, P, I64, P, P, P]
     L.dfhm_mlp_infer_noalloc.restype = C.c_int
     L.dfhm_mlp_noalloc_max_batch.argtypes = [P]

@@ -270,6 +270,20 @@ def train(net, data, walls, desc, targets, epochs=3, batch=8192, lr=1e-3, seed=0
     return dict(losses=losses, seconds=time.perf_counter() - t0, steps=steps, samples=steps * batch)
 
 
+def infer_ensemble(nets, x, scale, flux, err):
+    """Fluxes flux[B, 2] and error estimates err[B] of an ensemble of flux
+    heads on features x (dfhm_mlp_infer_ensemble); flux and err are
+    preallocated device tensors (views of larger ones allowed)."""
+    hs = (C.c_void_p * len(nets))(*[n._h for n in nets])
+    sc = np.ascontiguousarray(scale, np.float32)
+    st = _lib().dfhm_mlp_infer_ensemble(hs, len(nets), x.data_ptr(), x.shape[0],
+                                         sc.ctypes.data_as(C.c_void_p), flux.data_ptr(),
+                                         err.data_ptr())
+    if st != 0:
+        raise dfhm.DfhmError(st, "dfhm_mlp_infer_ensemble: " +
+                             _lib().dfhm_mlp_last_error(nets[0]._h).decode())
+
+
 def predict(nets, walls, t_windows, desc, targets, tau, batch=65536):
     """Network fluxes [W, K, 2] and fallback flags [W, K] for all windows,
     from one network or the mean of an ensemble (a list of networks)."""
@@ -284,22 +298,17 @@ def predict(nets, walls, t_windows, desc, targets, tau, batch=65536):
     t_of = torch.tensor(np.tile(t_windows, W), dtype=torch.float64, device=dev)
     n = W * K
     flux = torch.empty((n, 2), dtype=torch.float32, device=dev)
-    fb = torch.empty(n, dtype=torch.uint8, device=dev)
-    sc = np.ascontiguousarray(targets.scale8())
+    err = torch.empty(n, dtype=torch.float32, device=dev)
+    sc = targets.scale8()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for b0 in range(0, n, batch):
         b1 = min(n, b0 + batch)
         x = features(wall_of[b0:b1].contiguous(), t_of[b0:b1].contiguous(), sines_d, params_d, desc)
-        ys = [net.forward(x) for net in nets]
-        ptrs = (C.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
-        st = _lib().dfhm_mlp_decode_ensemble(ptrs, len(ys), b1 - b0,
-                                             sc.ctypes.data_as(C.c_void_p), float(tau),
-                                             flux[b0:].data_ptr(), fb[b0:].data_ptr(), _stream())
-        if st != 0:
-            raise dfhm.DfhmError(st, "dfhm_mlp_decode_ensemble")
+        infer_ensemble(nets, x, sc, flux[b0:b1], err[b0:b1])
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    fb = ~(err <= float(tau))            # a NaN estimate falls back
     return (flux.cpu().numpy().reshape(W, K, 2).astype(np.float64),
             fb.cpu().numpy().reshape(W, K).astype(bool), secs)
 
@@ -390,14 +399,10 @@ def serve(nets, walls, truth, desc, targets, tau, windows, dt=1.0, precision=dfh
 
         def network():
             x = features(wall_of, t_k, sines_d, params_d, desc)
-            ys = [net.forward(x) for net in nets]
-            ptrs = (C.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
             flux = torch.empty((W, 2), dtype=torch.float32, device=dev)
-            fb = torch.empty(W, dtype=torch.uint8, device=dev)
-            st = _lib().dfhm_mlp_decode_ensemble(ptrs, len(ys), W, sc.ctypes.data_as(C.c_void_p),
-                                                 float(tau), flux.data_ptr(), fb.data_ptr(), _stream())
-            if st != 0:
-                raise dfhm.DfhmError(st, "dfhm_mlp_decode_ensemble")
+            err = torch.empty(W, dtype=torch.float32, device=dev)
+            infer_ensemble(nets, x, sc, flux, err)
+            fb = ~(err <= float(tau))        # a NaN estimate falls back
             return flux.cpu().numpy().astype(np.float64), fb.cpu().numpy().astype(bool)
 
         network()                                   # warm-up (first launch of the kernels)

@@ -264,6 +264,57 @@ def test_gradients_layer_by_layer(dims, batch):
     net.close()
 
 
+def test_infer_ensemble_matches_member_forwards():
+    """dfhm_mlp_infer_ensemble over members the one-launch kernel covers
+    (width 512 and 256) and one it does not (width 136): the fluxes equal
+    dfhm_mlp_decode_ensemble of the members' dfhm_mlp_forward outputs bit for
+    bit, the error estimate is max_f of the member-mean estimate, and
+    members with different inputs are refused."""
+    dev = _dev()
+    rng = np.random.default_rng(19)
+    batch = 2999
+    nets = []
+    for width, seed in ((512, 21), (256, 22), (136, 23)):
+        dims = (584, width, 3, 8)
+        theta = mlp_ref.init(*dims[:3], seed=seed, n_out=8)
+        theta[-8:] = rng.normal(0, 0.2, 8)
+        theta[-4:] -= 8.0
+        net = _net(dims, batch, seed=seed)
+        net.set_params(theta)
+        nets.append(net)
+    from paper_1703_10119_amd import surrogate
+    x = torch.tensor(_bf16_bits(rng.normal(0, 1, (batch, 584))), device=dev)
+    scale = np.array([0.1, 1.2, -0.3, 0.9, 1.0, 0.5, -14.0, 0.8], np.float32)
+    flux = torch.empty((batch, 2), dtype=torch.float32, device=dev)
+    err = torch.empty(batch, dtype=torch.float32, device=dev)
+    surrogate.infer_ensemble(nets, x, scale, flux, err)
+    ys = [n.forward(x) for n in nets]
+    ptrs = (C.c_void_p * 3)(*[y.data_ptr() for y in ys])
+    f2 = torch.empty((batch, 2), dtype=torch.float32, device=dev)
+    fb = torch.empty(batch, dtype=torch.uint8, device=dev)
+    st = dfhm.load().dfhm_mlp_decode_ensemble(ptrs, 3, batch, scale.ctypes.data_as(C.c_void_p), 0.01,
+                                              f2.data_ptr(), fb.data_ptr(),
+                                              torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.equal(flux, f2)
+    m, sd = scale[0::2].astype(np.float64), scale[1::2].astype(np.float64)
+    e = np.zeros((batch, 2))
+    for y in ys:
+        yv = y.cpu().numpy().astype(np.float64)
+        u = yv[:, :2] * sd[:2] + m[:2]
+        e += sd[:2] * np.exp(0.5 * yv[:, 4:6]) + np.abs(u) * sd[2:] * np.exp(0.5 * yv[:, 6:8])
+    e = (e / 3).max(1)
+    got = err.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - e) <= 1e-5 * e + 1e-6 * np.abs(m[:2]).max() * sd[2:].max())
+    assert np.array_equal(fb.cpu().numpy().astype(bool), ~(got <= 0.01))
+    other = _net((40, 256, 2, 8), batch)
+    with pytest.raises(dfhm.DfhmError):
+        surrogate.infer_ensemble([nets[0], other], x, scale, flux, err)
+    for n in nets + [other]:
+        n.close()
+
+
 def test_infer_matches_forward_and_decode():
     """dfhm_mlp_infer = the network's forward pass followed by the flux
     decode: the same fluxes as dfhm_mlp_forward + dfhm_mlp_decode bit for bit,
