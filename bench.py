@@ -191,8 +191,10 @@ def roofline(dtype, cells, steps, ms, info, law=0):
                "kernel": "k_df_resident", "launch_ms": round(per_launch_s * 1e3, 3),
                "flops_per_cell": FLOPS_PER_CELL}
         if main_batch:
-            out["traffic_source"] = ("rocprofv3 FETCH_SIZE / WRITE_SIZE of a 1000-step launch, "
-                                     "profiles/counters_k_df_resident_65536x1001.md")
+            out["traffic_source"] = (
+                "rocprofv3 FETCH_SIZE / WRITE_SIZE of a 1000-step launch, "
+                "profiles/counters_k_df_resident_65536x1001.md" if out["traffic"] is not None else
+                "null: no 1000-step launch timed, or the committed counters are of other kernel sources")
             hw = counted_flops(dtype)
             if hw is not None:
                 # what the VALU executed (each exponential and division expands
