@@ -398,9 +398,11 @@ dfhm_status dfhm_mlp_decode(const float *y_dev, int64_t batch, const float *scal
 /* Decode an ensemble of n_nets networks trained on the same targets
  * (1 <= n_nets <= 4): y_dev is a host array of n_nets device output arrays,
  * each laid out as for dfhm_mlp_decode.  flux_dev[b][f] is the mean of the
- * members' u_f exp(l_f), and the predicted error the mean of their
- * sd(u_f) + |u_f| sd(l_f), compared with tau as there; n_nets = 1 gives
- * dfhm_mlp_decode's results.  DFHM_E_INVAL as there, and for a null y_dev or
+ * members' u_f exp(l_f); the predicted error adds, in quadrature, the mean
+ * of their sd(u_f) + |u_f| sd(l_f) and their disagreement (the population
+ * standard deviation of the members' fluxes over exp of their mean l_f),
+ * and is compared with tau as there; n_nets = 1 gives dfhm_mlp_decode's
+ * results.  DFHM_E_INVAL as there, and for a null y_dev or
  * member or n_nets outside [1, 4]. */
 dfhm_status dfhm_mlp_decode_ensemble(const float *const *y_dev, int32_t n_nets, int64_t batch,
                                      const float *scale, float tau, float *flux_dev,
@@ -422,7 +424,7 @@ dfhm_status dfhm_mlp_infer(dfhm_mlp *m, const uint16_t *x_dev, int64_t batch, co
  * (n_in), stream and device: every member's forward pass on x_dev, then the
  * ensemble decode (as dfhm_mlp_decode_ensemble): flux_dev[b][f] the mean of
  * the members' fluxes, err_est_dev[b] the maximum over the two fields of the
- * mean of their error estimates.  Device pointers, queued on the members'
+ * ensemble's error estimate defined there.  Device pointers, queued on the members'
  * stream.  DFHM_E_INVAL for a null member, members that differ, n_nets
  * outside [1, 4], and as dfhm_mlp_infer for each member; the message goes
  * to the first member's dfhm_mlp_last_error. */

@@ -611,11 +611,15 @@ __global__ void k_features(const int32_t *__restrict__ wall_of, const double *__
 // y[b] = (u_q, u_g, l_q, l_g, s_uq, s_ug, s_lq, s_lg), s = log variance.
 // flux_f = u_f exp(l_f).  The predicted error relative to the RMS flux is
 // e_f = sd(u_f) + |u_f| sd(l_f) to first order, sd = std * exp(s / 2);
-// fallback when e_f > tau for either field.  scale[8] = (mean, std) of
-// u_q, u_g, l_q, l_g.  With several networks (an ensemble trained on the
-// same targets), flux_f and e_f are the means over the members.  Outputs
-// (each optional): flux[b][2], err[b] = max_f e_f, fallback[b].  A member's
-// outputs of sample b start at y[k] + ld * b.
+// fallback when the estimate exceeds tau for either field.  scale[8] =
+// (mean, std) of u_q, u_g, l_q, l_g.  With several networks (an ensemble
+// trained on the same targets) flux_f is the members' mean, and the estimate
+// adds their disagreement to their mean predicted error in quadrature:
+// sqrt(E_f^2 + D_f^2), E_f = mean_k e_fk,
+// D_f = (population) std_k of flux_fk over exp(mean_k l_fk), the members'
+// spread relative to their mean predicted RMS; one network gives e_f itself.
+// Outputs (each optional): flux[b][2], err[b] = max_f estimate, fallback[b].
+// A member's outputs of sample b start at y[k] + ld * b.
 struct DecodeScale { float m[4], s[4]; };
 constexpr int kMaxEnsemble = 4;
 struct DecodeNets {
@@ -633,19 +637,32 @@ __global__ void k_decode(DecodeNets nets, int64_t batch, DecodeScale sc, float t
     float emax = 0.f;
     bool fb = false;
     for (int f = 0; f < 2; ++f) {
-        float fl = 0.f, e = 0.f;
+        float fk[kMaxEnsemble];
+        float fl = 0.f, e = 0.f, lm = 0.f;
 #pragma unroll
         for (int k = 0; k < kMaxEnsemble; ++k) {
+            fk[k] = 0.f;
             if (k < nets.n) {
                 const float *o = nets.y[k] + (int64_t)nets.ld * b;
                 const float u = o[f] * sc.s[f] + sc.m[f];
                 const float lg = o[2 + f] * sc.s[2 + f] + sc.m[2 + f];
-                fl += u * __expf(lg);
+                fk[k] = u * __expf(lg);
+                fl += fk[k];
+                lm += lg;
                 e += sc.s[f] * __expf(0.5f * o[4 + f]) + fabsf(u) * sc.s[2 + f] * __expf(0.5f * o[6 + f]);
             }
         }
-        if (flux) flux[2 * b + f] = fl * inv;
+        fl *= inv;
+        if (flux) flux[2 * b + f] = fl;
         e *= inv;
+        if (nets.n > 1) {
+            float v = 0.f;
+#pragma unroll
+            for (int k = 0; k < kMaxEnsemble; ++k)
+                if (k < nets.n) v += (fk[k] - fl) * (fk[k] - fl);
+            const float d = sqrtf(v * inv) * __expf(-lm * inv);
+            e = sqrtf(e * e + d * d);
+        }
         fb = fb || !(e <= tau);
         emax = (f == 0 || !(e <= emax)) ? e : emax;   // a NaN estimate propagates
     }

@@ -300,11 +300,16 @@ def test_infer_ensemble_matches_member_forwards():
     assert torch.equal(flux, f2)
     m, sd = scale[0::2].astype(np.float64), scale[1::2].astype(np.float64)
     e = np.zeros((batch, 2))
+    fks, lgs = [], []
     for y in ys:
         yv = y.cpu().numpy().astype(np.float64)
         u = yv[:, :2] * sd[:2] + m[:2]
+        lg = yv[:, 2:4] * sd[2:] + m[2:]
+        fks.append(u * np.exp(lg))
+        lgs.append(lg)
         e += sd[:2] * np.exp(0.5 * yv[:, 4:6]) + np.abs(u) * sd[2:] * np.exp(0.5 * yv[:, 6:8])
-    e = (e / 3).max(1)
+    dis = np.std(np.array(fks), axis=0) / np.exp(np.mean(np.array(lgs), axis=0))
+    e = np.sqrt((e / 3) ** 2 + dis ** 2).max(1)
     got = err.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(got - e) <= 1e-5 * e + 1e-6 * np.abs(m[:2]).max() * sd[2:].max())
     assert np.array_equal(fb.cpu().numpy().astype(bool), ~(got <= 0.01))
@@ -478,15 +483,20 @@ def test_decode_and_fallback_flags():
 
 
 def test_decode_ensemble_is_the_member_mean():
-    """Ensemble decode against its definition: flux and predicted error are
-    the means of the members' values; one member gives dfhm_mlp_decode's
-    results bit for bit; bad member counts or a null member are refused."""
+    """Ensemble decode against its definition: the flux is the members' mean,
+    the predicted error their mean estimate and their disagreement in
+    quadrature; one member gives dfhm_mlp_decode's results bit for bit; bad
+    member counts or a null member are refused."""
     dev = _dev()
     rng = np.random.default_rng(17)
     B, K = 777, 3
     ys = []
+    base = rng.normal(0, 1, (B, 4))
     for _ in range(K):
-        y = rng.normal(0, 1, (B, 8)).astype(np.float32)
+        # members that agree to a few 1e-3 (so that their disagreement and
+        # their variance heads both matter near tau)
+        y = np.empty((B, 8), np.float32)
+        y[:, :4] = base + rng.normal(0, 3e-3, (B, 4))
         y[:, 4:] = rng.uniform(-20, -4, (B, 4))
         ys.append(y)
     scale = np.array([0.1, 1.2, -0.3, 0.9, 1.0, 0.5, -14.0, 0.8], np.float32)
@@ -504,14 +514,20 @@ def test_decode_ensemble_is_the_member_mean():
     want = np.zeros((B, 2))
     e = np.zeros((B, 2))
     bound = np.zeros((B, 2))
+    fks, lgs = [], []
     for y in ys:
         yv = y.astype(np.float64)
         u = yv[:, :2] * sd[:2] + m[:2]
         lg = yv[:, 2:4] * sd[2:] + m[2:]
         want += u * np.exp(lg) / K
+        fks.append(u * np.exp(lg))
+        lgs.append(lg)
         e += (sd[:2] * np.exp(0.5 * yv[:, 4:6]) + np.abs(u) * sd[2:] * np.exp(0.5 * yv[:, 6:8])) / K
         bound += (1e-6 * (np.abs(yv[:, :2] * sd[:2]) + np.abs(m[:2])) * np.exp(lg)
                   + 1e-5 * np.abs(u * np.exp(lg))) / K
+    # the members' disagreement over their mean predicted RMS, in quadrature
+    dis = np.std(np.array(fks), axis=0) / np.exp(np.mean(np.array(lgs), axis=0))
+    e = np.sqrt(e ** 2 + dis ** 2)
     f = flux.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(f - want) <= bound + 1e-6 * np.abs(want))
     flag = np.any(e > tau, axis=1)
