@@ -497,6 +497,42 @@ def test_full_size_batch_sampled(pname, prec):
     s.close()
 
 
+@pytest.mark.parametrize("pname,prec", PRECS)
+def test_full_size_batch_over_its_horizon_sampled(pname, prec):
+    """The full 65,536 x 1001 batch over its 100,000-step horizon in the
+    benchmark's launch configuration (resident, 1000-step chunks); eight walls
+    sampled across the batch are re-run alone by the oracle (walls are
+    independent), fields and flux integrals compared, range-normalised too.
+
+    Flux bar over this horizon: the applied flux is h (T_air - T_s), a
+    difference about 30x smaller than T itself, so a surface temperature
+    within the field bar of 1e-12 of max |T| (3e-10 K) moves the flux by up
+    to ~3e-11 of its largest value, and the integral of an oscillating flux
+    over 1e5 steps carries that with a factor of a few: 1e-10 (FP64).  The
+    short runs above stay within 1e-11."""
+    walls = wl.uniform_batch(65536, seed=202, nx=1001)
+    cfg = wl.default_config(dt=1.0)
+    steps = 100000
+    say(f"full size 65536x1001 x{steps} {pname}")
+    s = dfhm.Solver(walls, cfg, precision=prec, schedule=dfhm.SCHED_RESIDENT)
+    s.step(steps)
+    s.sync()
+    idx = [0, 9001, 17777, 26000, 38000, 47123, 56000, 65535]
+    ref = _PerWall(wl.subset(walls, idx), cfg, steps)
+    T, P = (np.concatenate(v) for v in zip(*[s.fields(w) for w in idx]))
+    Tr, Pr = ref.all_fields(0)
+    _, integ = s.fluxes()
+    _, int_r = ref.fluxes()
+    out = dict(T=rel(T, Tr), P=rel(P, Pr), T_rng=rng(T, Tr), P_rng=rng(P, Pr),
+               flux_int=rel(integ[idx], int_r))
+    say("  sampled walls: " + " ".join(f"{k}={v:.2e}" for k, v in out.items()))
+    assert out["T"] <= TOL[prec] and out["P"] <= TOL[prec], out
+    if prec == dfhm.FP32:
+        assert out["T_rng"] <= 1e-5 and out["P_rng"] <= 1e-5, out
+    assert out["flux_int"] <= (1e-10 if prec == dfhm.FP64 else FTOL[prec]), out
+    s.close()
+
+
 def test_torch_arena_and_library_arena_agree():
     walls = wl.layered_batch(30, seed=9)
     cfg = wl.default_config(dt=1.0)
