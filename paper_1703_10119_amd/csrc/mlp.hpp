@@ -35,31 +35,32 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // instructions in the GEMM epilogues).
 __device__ __forceinline__ float gelu(float z)
 {
-    const float az = fabsf(z);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
-    // h = Phi(-|z|): the coefficients are a_i / 2, and exp(-z^2 / 2) = 2^(-z^2 / (2 ln 2))
+    // with w = z / 2: z Phi(z) = w + |z| (1/2 - Phi(-|z|)) for either sign,
+    // and t = 1 / (1 + p |z| / sqrt 2) = 1 / (1 + 2 p |w| / sqrt 2)
+    const float w = 0.5f * z;
+    const float t = __builtin_amdgcn_rcpf(fmaf(2.0f * (0.3275911f * 0.70710678f), fabsf(w), 1.0f));
+    // Phi(-|z|) = p e: the coefficients are a_i / 2, and exp(-z^2 / 2) = 2^(-2 w^2 / ln 2)
     const float p = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 0.5307027145f, -0.7265760135f), 0.7107068705f),
                                      -0.142248368f), 0.127414796f);
-    const float h = p * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
-    // z (1 - h) for z >= 0 and z h below: max(z, 0) - |z| h
-    return fmaf(-az, h, fmaxf(z, 0.f));
+    const float e = __builtin_amdgcn_exp2f((-4.0f * 0.72134752f * w) * w);
+    return fmaf(fabsf(z), fmaf(-p, e, 0.5f), w);
 }
 // The same GELU on four values, written step by step across them so that
 // four independent chains interleave (same operations per value, so the
 // results equal gelu()'s bit for bit).
 __device__ __forceinline__ f32x4 gelu4(f32x4 z)
 {
-    f32x4 az, t, p, e, r;
+    f32x4 w, t, p, e, r;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        az[q] = fabsf(z[q]);
-        t[q] = fmaf(0.3275911f * 0.70710678118654752f, az[q], 1.0f);
-        e[q] = -0.72134752044448170f * z[q];
+        w[q] = 0.5f * z[q];
+        t[q] = fmaf(2.0f * (0.3275911f * 0.70710678f), fabsf(w[q]), 1.0f);
+        e[q] = (-4.0f * 0.72134752f * w[q]) * w[q];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         t[q] = __builtin_amdgcn_rcpf(t[q]);
-        e[q] = __builtin_amdgcn_exp2f(e[q] * z[q]);
+        e[q] = __builtin_amdgcn_exp2f(e[q]);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) p[q] = fmaf(t[q], 0.5307027145f, -0.7265760135f);
@@ -70,7 +71,7 @@ __device__ __forceinline__ f32x4 gelu4(f32x4 z)
 #pragma unroll
     for (int q = 0; q < 4; ++q) p[q] = fmaf(t[q], p[q], 0.127414796f);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = fmaf(-az[q], (t[q] * p[q]) * e[q], fmaxf(z[q], 0.f));
+    for (int q = 0; q < 4; ++q) r[q] = fmaf(fabsf(z[q]), fmaf(-(t[q] * p[q]), e[q], 0.5f), w[q]);
     return r;
 }
 // Its derivative (erf form, library erff).
