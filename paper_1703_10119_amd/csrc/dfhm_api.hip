@@ -607,14 +607,13 @@ template <typename R, int NPT, int NT, int MODE, int LAW>
 void launch_res(dfhm_ctx *c, int k)
 {
     refresh_io(c);
-    static bool attr_set = false;   // the largest tables need more than 64 KB of LDS
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT, MODE, LAW>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)res_lds_bytes<R>(NT, NPT, kResMaxWalls, kResMaxRooms,
-                                                        MODE == kModeExt, LAW));
-        attr_set = true;
-    }
+    // the largest tables need more than 64 KB of LDS; set on every launch (a
+    // host-side call, once per chunk), so that every device the library runs
+    // on and every thread sees it
+    (void)hipFuncSetAttribute((const void *)k_df_resident<R, NPT, NT, MODE, LAW>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)res_lds_bytes<R>(NT, NPT, kResMaxWalls, kResMaxRooms,
+                                                    MODE == kModeExt, LAW));
     // LDS records sized by the largest wall / zone count of a workgroup of
     // this packing (at least one of each)
     const int mw = std::max(1, c->max_wpb), mr = std::max(1, c->max_rpb);

@@ -157,12 +157,10 @@ bool fused_ok(const dfhm_mlp *m)
 template <int NJ>
 void launch_fused(dfhm_mlp *m, const FusedNet &net, const uint16_t *x, int64_t batch, float *y)
 {
-    static bool attr_set = false;   // above the default 64 KB of LDS
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_mlp_infer_fused<NJ>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes<NJ>());
-        attr_set = true;
-    }
+    // above the default 64 KB of LDS; set on every call, so that every
+    // device the library runs on and every thread sees it
+    (void)hipFuncSetAttribute((const void *)k_mlp_infer_fused<NJ>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_lds_bytes<NJ>());
     hipLaunchKernelGGL(k_mlp_infer_fused<NJ>, dim3((unsigned)((batch + FI_M - 1) / FI_M)),
                        dim3(64 * FI_NW), fused_lds_bytes<NJ>(), m->stream, net, x, m->cfg.n_in, batch,
                        y, kOutPad);
