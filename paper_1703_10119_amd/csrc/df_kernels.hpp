@@ -4,8 +4,9 @@
 //   workgroup = one tile of 255 consecutive nodes of one wall plus one halo
 //   lane on its left; lane i owns node j = j0 - 1 + i.  Each lane evaluates
 //   the face j+1/2 at the face-averaged state of level n (Sec. 3.1); the
-//   faces are exchanged through LDS so every face is evaluated once.  Lane 0
-//   only contributes its face.  Moisture is updated first and heat uses the
+//   faces and the nodes' level-n state are exchanged through LDS, so every
+//   face is evaluated once and every level is read once, all reads issued
+//   before the face arithmetic.  Lane 0 only contributes its face.  Moisture is updated first and heat uses the
 //   new vapour pressure (App. A, eq. DF_eq2b).  Surface lanes evaluate the
 //   outdoor air at t^n in FP64 (or read the zone air of level n), apply the
 //   DF-averaged Robin half cell (eq. bc_v) and update the wall's applied flux
@@ -185,6 +186,7 @@ k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
             const int64_t *__restrict__ step_base, int step_off, RunConst rc)
 {
     __shared__ R s_kT[kStreamBlock], s_kM[kStreamBlock], s_kX[kStreamBlock];
+    __shared__ R s_T[kStreamBlock], s_P[kStreamBlock];
     __shared__ double s_lay[kMaxLayers][L_COUNT];
 
     const int2 tile = tiles[blockIdx.x];
@@ -211,9 +213,12 @@ k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
     const R thr = Store<R>::thref(W);
     const R pr = Store<R>::pref(W);
 
-    R Tj = 0, Pj = 0, Tr = 0, Pr = 0;
+    // every level read is issued here, before the face arithmetic: the left
+    // neighbour comes from the lane on the left through LDS
+    R Tj = 0, Pj = 0, Tr = 0, Pr = 0, Tm = 0, Pm = 0;
     const bool in_wall = j >= 0 && j < nx;
     if (in_wall) { Tj = Tc[j]; Pj = Pc[j]; }
+    if (in_wall && i > 0) { Tm = Tp[j]; Pm = Pp[j]; }
     KCoef<R> kr = {0, 0, 0};
     if (j >= 0 && j < nx - 1) {
         Tr = Tc[j + 1];
@@ -240,6 +245,8 @@ k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
     s_kT[i] = kr.kT;
     s_kM[i] = kr.kM;
     s_kX[i] = kr.kX;
+    s_T[i] = Tj;
+    s_P[i] = Pj;
     __syncthreads();
     if (i == 0 || !in_wall) return;
 
@@ -251,16 +258,15 @@ k_df_stream(const WallDev *__restrict__ walls, const int2 *__restrict__ tiles,
     if constexpr (LAW == 1) c = t1_law_c<R>(m, th, P, (R)rc.cw);
     else c = law_c<R>(m, P / psat_th(th), th);
     const R r = (R)W.r;
-    const R Tm = Tp[j], Pm = Pp[j];
     R Tn, Pn;
     if (j > 0 && j < nx - 1) {
-        R Tl = Tc[j - 1], Pl = Pc[j - 1];
+        R Tl = s_T[i - 1], Pl = s_P[i - 1];
         df_interior<R>(r, c, kl, kr, Tm, Pm, Tl, Pl, Tr, Pr, Tn, Pn);
     } else {
         const int side = j == 0 ? 0 : 1;
         const KCoef<R> k = side == 0 ? kr : kl;
-        R Tnb = side == 0 ? Tr : Tc[j - 1];
-        R Pnb = side == 0 ? Pr : Pc[j - 1];
+        R Tnb = side == 0 ? Tr : s_T[i - 1];
+        R Pnb = side == 0 ? Pr : s_P[i - 1];
         double Tinf, Pinf;
         ambient(W, side, (double)n * rc.dt, roomT, roomP, Tinf, Pinf);
         // radiation at t^n: incident flux, long-wave exchange on the zone side

@@ -48,9 +48,17 @@ constexpr int kResMaxRooms = 16;   // zones per workgroup
 constexpr int kResMaxLinks = 8;    // inter-zone links per zone
 
 struct ResBlock {
-    int32_t w_begin, w_end;        // range in block_walls (ascending wall ids)
+    int32_t w_begin, w_end;        // range in the slot table (ascending wall ids)
     int32_t r_begin, r_end;        // range in block_rooms
     int32_t n_nodes, pad;
+};
+
+// One wall of a workgroup: its id, its node range in the workgroup
+// ([wstart, wend), lanes own consecutive nodes) and its first node in the
+// level arrays; written by the packer, so that the set-up reads one record
+// per wall instead of walking the wall table.
+struct ResSlot {
+    int32_t wid, wstart, wend, off;
 };
 
 struct Shape {
@@ -77,7 +85,7 @@ template <typename R> struct WallRec {
     R cc[4][4];               // per layer: c0 / r, cM0 / r, theta ref, Pv ref
     R fk[8][4];               // per entry: k0, kM0 (layer, interface with the next, none),
                               // theta ref, Pv ref
-    int32_t wstart, wend, wid, wroom, wside, pad[3];
+    int32_t wstart, wend, wid, wroom, wside, off, pad[2];
 };
 // A wall's radiative sources (extended variant only, in LDS after the wall
 // records, so that the other variants keep the smaller footprint).
@@ -98,7 +106,6 @@ struct RoomRec {
 // memory there, so that they do not occupy scalar registers through the loop).
 struct ResIO {
     void *T[2], *P[2];
-    const WallDev *walls;
     double *flux, *roomT, *roomP;
     int *bad;
 };
@@ -201,7 +208,7 @@ template <typename R, int NPT, int NT, int MODE, int LAW> constexpr int res_wave
 // harmonic interface means of the scale tables still apply).
 template <typename R, int NPT, int NT, int MODE, int LAW>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(res_waves_per_eu<R, NPT, NT, MODE, LAW>())))
-k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ block_walls,
+k_df_resident(const ResBlock *__restrict__ blocks, const ResSlot *__restrict__ slots,
               const int32_t *__restrict__ block_rooms, const WallDev *__restrict__ walls,
               const R *T0b, const R *T1b, const R *P0b, const R *P1b,
               const uint8_t *__restrict__ lay, const RoomDev *__restrict__ rooms,
@@ -237,18 +244,17 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     const int nrb = B.r_end - B.r_begin;
     const int64_t n0 = *step_base;
 
-    // ---- run constants, wall table, zone table
+    // ---- run constants, wall slots, zone table
     if (t == 0) {
         s_rc[0] = rc.dt; s_rc[1] = rc.Lv; s_rc[2] = rc.rho_a;
         s_rc[3] = rc.c_pa; s_rc[4] = rc.c_pv; s_rc[5] = rc.Pv_ref;
-        int acc = 0;
-        for (int s = 0; s < nwb; ++s) {
-            int w = block_walls[B.w_begin + s];
-            wr[s].wid = w;
-            wr[s].wstart = acc;
-            acc += walls[w].nx;
-            wr[s].wend = acc;
-        }
+    }
+    if (t < nwb) {
+        const ResSlot S = slots[B.w_begin + t];
+        wr[t].wid = S.wid;
+        wr[t].wstart = S.wstart;
+        wr[t].wend = S.wend;
+        wr[t].off = S.off;
     }
     if (ZON && t < nrb) {
         int r = block_rooms[B.r_begin + t];
@@ -349,7 +355,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
     const bool amb_lane = ta >= 0 && ta < 2 * nwb;
     const int amb_slot = ta >> 1, amb_side = ta & 1;
     if (amb_lane) {
-        const WallDev &W = walls[block_walls[B.w_begin + amb_slot]];
+        const WallDev &W = walls[wr[amb_slot].wid];
         const double *ST = W.Tamb[amb_side], *SR = W.RHamb[amb_side];
         const double t0 = (double)n0 * rc.dt;
         double *st = wr[amb_slot].rot[amb_side];
@@ -398,15 +404,14 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
                       ((uint32_t)((kWalls + offsetof(WallRec<R>, fk) + sizeof(R) * 4 * kFaceNone) >> 4) << 16);
             if (b < B.n_nodes) {
                 while (b >= wr[slot].wend) ++slot;
-                const WallDev &W = walls[wr[slot].wid];
-                const int j = b - wr[slot].wstart;
-                const int64_t g = (int64_t)W.off + j;
+                const int j = b - wr[slot].wstart, nx = wr[slot].wend - wr[slot].wstart;
+                const int64_t g = (int64_t)wr[slot].off + j;
                 Ta_[q] = Tp[g]; Pa_[q] = Pp[g];
                 Tb_[q] = Tc[g]; Pb_[q] = Pc[g];
                 const int la = lay[g];
                 int fe = kFaceNone;
-                if (j < W.nx - 1) fe = lay[g + 1] == la ? 2 * la : 2 * la + 1;
-                info[q] = slot | ((j == 0) << 8) | ((j == W.nx - 1) << 9) | (1 << 10) | (la << 11) |
+                if (j < nx - 1) fe = lay[g + 1] == la ? 2 * la : 2 * la + 1;
+                info[q] = slot | ((j == 0) << 8) | ((j == nx - 1) << 9) | (1 << 10) | (la << 11) |
                           (fe << 13);
                 const int rb = (int)(kWalls + sizeof(WallRec<R>) * (size_t)slot);
                 const uint32_t co = (uint32_t)(rb + (int)(offsetof(WallRec<R>, cc) + sizeof(R) * 4 * la));
@@ -794,8 +799,7 @@ k_df_resident(const ResBlock *__restrict__ blocks, const int32_t *__restrict__ b
         if (f & (1 << 10)) {
             const int b = t * NPT + q;
             const int s = f & 0xff;
-            const WallDev &W = O.walls[wr[s].wid];
-            const int64_t g = (int64_t)W.off + (b - wr[s].wstart);
+            const int64_t g = (int64_t)wr[s].off + (b - wr[s].wstart);
             if (!(isfinite(Tb_[q]) && isfinite(Pb_[q]))) nonfinite = 1;
             Tw_cur[g] = Tb_[q];
             Pw_cur[g] = Pb_[q];

@@ -55,7 +55,7 @@ struct dfhm_ctx {
     // resident packing
     void *pack_mem = nullptr;
     ResBlock *d_blocks = nullptr;
-    int32_t *d_block_walls = nullptr;
+    ResSlot *d_slots = nullptr;
     int32_t *d_block_rooms = nullptr;
     int n_blocks = 0, max_wpb = 0, max_rpb = 0;
     double pack_eff = 0.0;
@@ -249,7 +249,7 @@ dfhm_status check_bad(dfhm_ctx *c)
 }
 
 template <typename R>
-dfhm_status launch_stream_step(dfhm_ctx *c, int off)
+void launch_stream_step(dfhm_ctx *c, int off)
 {
     auto kern = c->cfg.law == DFHM_LAW_TABLE1
                     ? (c->extended ? k_df_stream<R, true, 1> : k_df_stream<R, false, 1>)
@@ -258,7 +258,6 @@ dfhm_status launch_stream_step(dfhm_ctx *c, int off)
                        c->d_walls, c->d_tiles, (R *)c->d_T[0], (R *)c->d_T[1], (R *)c->d_P[0],
                        (R *)c->d_P[1], c->d_lay, c->d_roomT, c->d_roomP, c->d_rooms,
                        c->d_room_walls, c->d_flux, c->d_bad, c->d_step, off, c->rc);
-    return DFHM_OK;
 }
 
 template <typename R>
@@ -489,7 +488,8 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
         if (cap - b.used > 0 && b.walls < wcap) free_cap.emplace(cap - b.used, chosen);
     }
     std::vector<ResBlock> blocks(bins.size());
-    std::vector<int32_t> bw, br;
+    std::vector<ResSlot> bw;
+    std::vector<int32_t> br;
     int maxw = 0, maxr = 0;
     for (size_t i = 0; i < bins.size(); ++i) {
         std::vector<int32_t> ws;
@@ -502,7 +502,12 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
         std::sort(rs.begin(), rs.end());
         ResBlock &B = blocks[i];
         B.w_begin = (int32_t)bw.size();
-        bw.insert(bw.end(), ws.begin(), ws.end());
+        int32_t at = 0;
+        for (int32_t w : ws) {
+            const int32_t nx = c->walls[w].nx;
+            bw.push_back({w, at, at + nx, c->walls[w].off});
+            at += nx;
+        }
         B.w_end = (int32_t)bw.size();
         B.r_begin = (int32_t)br.size();
         br.insert(br.end(), rs.begin(), rs.end());
@@ -516,7 +521,7 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     size_t ob = take(sizeof(ResBlock) * blocks.size());
-    size_t ow = take(sizeof(int32_t) * bw.size());
+    size_t ow = take(sizeof(ResSlot) * bw.size());
     size_t orr = take(sizeof(int32_t) * br.size());
     size_t oio = take(sizeof(ResIO));
     if (c->pack_mem) { (void)hipStreamSynchronize(c->stream); (void)hipFree(c->pack_mem); c->pack_mem = nullptr; }
@@ -524,12 +529,12 @@ dfhm_status pack(dfhm_ctx *c, int nt, int npt)
     if (hipMalloc(&mem, o) != hipSuccess) return fail(c, DFHM_E_NOMEM, "packing tables");
     c->pack_mem = mem;
     c->d_blocks = (ResBlock *)((char *)mem + ob);
-    c->d_block_walls = (int32_t *)((char *)mem + ow);
+    c->d_slots = (ResSlot *)((char *)mem + ow);
     c->d_block_rooms = (int32_t *)((char *)mem + orr);
     c->d_io = (ResIO *)((char *)mem + oio);
     c->io_valid = false;
     HIP_TRY(c, hipMemcpyAsync(c->d_blocks, blocks.data(), sizeof(ResBlock) * blocks.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->d_block_walls, bw.data(), sizeof(int32_t) * bw.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_slots, bw.data(), sizeof(ResSlot) * bw.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_block_rooms, br.data(), sizeof(int32_t) * br.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->n_blocks = (int)blocks.size();
@@ -592,7 +597,6 @@ void refresh_io(dfhm_ctx *c)
     ResIO io{};
     io.T[0] = c->d_T[0]; io.T[1] = c->d_T[1];
     io.P[0] = c->d_P[0]; io.P[1] = c->d_P[1];
-    io.walls = c->d_walls;
     io.flux = c->d_flux;
     io.roomT = c->d_roomT;
     io.roomP = c->d_roomP;
@@ -619,7 +623,7 @@ void launch_res(dfhm_ctx *c, int k)
     const int mw = std::max(1, c->max_wpb), mr = std::max(1, c->max_rpb);
     hipLaunchKernelGGL((k_df_resident<R, NPT, NT, MODE, LAW>), dim3(c->n_blocks), dim3(NT),
                        res_lds_bytes<R>(NT, NPT, mw, mr, MODE == kModeExt, LAW), c->stream, c->d_blocks,
-                       c->d_block_walls,
+                       c->d_slots,
                        c->d_block_rooms, c->d_walls, (const R *)c->d_T[0], (const R *)c->d_T[1],
                        (const R *)c->d_P[0], (const R *)c->d_P[1], c->d_lay, c->d_rooms,
                        c->d_roomT, c->d_roomP, c->d_go, c->d_qh, c->d_flux, c->d_step, c->d_io,

@@ -211,6 +211,34 @@ def test_rooms_coupled(pname, prec, sname, sched):
 
 
 @pytest.mark.parametrize("pname,prec", PRECS)
+@pytest.mark.parametrize("kind", ["uniform", "layered", "rooms"])
+def test_odd_and_even_launch_lengths(kind, pname, prec):
+    """Resident launches of odd and even step counts (1, 36, 37 x 3, 5): an
+    odd count enters the kernel's paired step loop at its second step."""
+    rooms = None
+    if kind == "uniform":
+        walls, dt = wl.uniform_batch(16, seed=212, nx=1001), 1.0
+    elif kind == "layered":
+        walls, dt = wl.layered_batch(60, seed=313), 1.0
+    else:
+        walls, rooms = wl.building_batch(3, seed=414, dt=10.0)
+        dt = 10.0
+    cfg = wl.default_config(dt=dt)
+    say(f"odd/even launch lengths {kind} {pname}")
+    ref = oracle_run(walls, cfg, 153, rooms=rooms)
+    s = dfhm.Solver(walls, cfg, rooms=rooms, precision=prec, schedule=dfhm.SCHED_RESIDENT, chunk=37)
+    for k in (1, 36, 111, 5):
+        s.step(k)
+    s.sync()
+    assert s.n == 153
+    compare(s, ref, prec, f"odd/even {kind} {pname}")
+    if rooms is not None:
+        Ta, Pa = s.rooms()
+        Tar, Par = ref.rooms()
+        assert rel(Ta, Tar) <= TOL[prec] and rel(Pa, Par) <= TOL[prec]
+
+
+@pytest.mark.parametrize("pname,prec", PRECS)
 @pytest.mark.parametrize("sname,sched", SCHEDS)
 def test_rooms_radiating(pname, prec, sname, sched):
     """6 rooms with long-wave exchange among their surfaces (eps 0.5 / 0.9,
