@@ -1258,16 +1258,17 @@ dfhm_status dfhm_implicit_create(const dfhm_implicit_config *cfg, const dfhm_wal
     ic->nw = n_walls;
     ic->walls.resize(n_walls);
     for (int64_t i = 0; i < n_walls; ++i) fill_wall(ic->walls[i], walls[i], 0);
-    // groups of 64 consecutive walls, each a node-major block padded to its longest wall
+    // groups of 32 consecutive walls (one wave, two lanes per wall), each a
+    // node-major block padded to its longest wall
     int64_t base = 0;
-    for (int64_t w0 = 0; w0 < n_walls; w0 += kImpLanes) {
+    for (int64_t w0 = 0; w0 < n_walls; w0 += kImpWalls) {
         ImpGroup g;
         g.base = base;
         g.w0 = (int32_t)w0;
-        g.nw = (int32_t)std::min<int64_t>(kImpLanes, n_walls - w0);
+        g.nw = (int32_t)std::min<int64_t>(kImpWalls, n_walls - w0);
         int maxnx = 0;
         for (int k = 0; k < g.nw; ++k) maxnx = std::max(maxnx, (int)walls[w0 + k].nx);
-        base += (int64_t)maxnx * kImpLanes;
+        base += (int64_t)maxnx * kImpWalls;
         ic->groups.push_back(g);
     }
     ic->slots = base;
@@ -1317,13 +1318,13 @@ dfhm_status dfhm_implicit_step_n(dfhm_implicit *ic, int64_t n_steps)
 dfhm_status dfhm_implicit_get_fields(dfhm_implicit *ic, int64_t wall, double *T, double *Pv)
 {
     if (!ic || !T || !Pv || wall < 0 || wall >= ic->nw) return DFHM_E_INVAL;
-    const ImpGroup &g = ic->groups[wall / kImpLanes];
-    const int lane = (int)(wall % kImpLanes), nx = ic->walls[wall].nx;
+    const ImpGroup &g = ic->groups[wall / kImpWalls];
+    const int slot = (int)(wall % kImpWalls), nx = ic->walls[wall].nx;
     const int p = (int)(ic->n & 1);
-    // one strided copy per field: element j of the wall is at base + 64 j + lane
-    if (hipMemcpy2DAsync(T, sizeof(double), ic->A.T[p] + g.base + lane, sizeof(double) * kImpLanes,
+    // one strided copy per field: element j of the wall is at base + 32 j + slot
+    if (hipMemcpy2DAsync(T, sizeof(double), ic->A.T[p] + g.base + slot, sizeof(double) * kImpWalls,
                          sizeof(double), nx, hipMemcpyDeviceToHost, ic->stream) != hipSuccess ||
-        hipMemcpy2DAsync(Pv, sizeof(double), ic->A.P[p] + g.base + lane, sizeof(double) * kImpLanes,
+        hipMemcpy2DAsync(Pv, sizeof(double), ic->A.P[p] + g.base + slot, sizeof(double) * kImpWalls,
                          sizeof(double), nx, hipMemcpyDeviceToHost, ic->stream) != hipSuccess ||
         hipStreamSynchronize(ic->stream) != hipSuccess) {
         ic->err = "copy failed";

@@ -61,6 +61,27 @@ def test_layered_walls_match_oracle():
     ic.close()
 
 
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_short_and_mixed_walls_match_oracle(theta):
+    """Two lanes solve each wall, eliminating from both surfaces towards the
+    middle node m = (nx - 1) / 2: walls of 3-8 nodes (m next to a surface,
+    halves of equal and of unequal length) beside walls of 9-101 nodes in one
+    wave, and a second, partly filled group of lanes."""
+    sizes = [3, 4, 5, 6, 7, 8] + [9 + 3 * k for k in range(31)]
+    walls = wl.concat(*[wl.uniform_batch(1, seed=60 + i, nx=n, L=0.01 * n)
+                        for i, n in enumerate(sizes)])
+    ic = dfhm.Implicit(walls, dt=20.0, theta=theta, eta=1e-12, max_iters=200)
+    ic.step(25)
+    worst = 0.0
+    for w in list(range(8)) + [20, 31, 32, 36]:
+        T, P = ic.fields(w)
+        Tr, Pr, _ = oracle.implicit_run(walls, w, 20.0, wl.LV, 25, theta=theta, eta=1e-12)
+        worst = max(worst, rel(T, Tr), rel(P, Pr))
+    print("short/mixed worst", worst)
+    assert worst <= TOL
+    ic.close()
+
+
 def test_implicit_and_df_agree_at_small_dt():
     """Two schemes of the same problem: Crank-Nicolson and DF at dt = 1 s over
     one hour differ only by their O(dt^2) truncation (and DF's
