@@ -52,8 +52,6 @@ __global__ void k_imp_init(const WallDev *__restrict__ walls, const ImpGroup *__
 // the coefficient evaluations inside the sweeps read no global memory.
 struct ImpLaw {
     const double *p;     // &s_law[0][lane]
-    int law;             // 0: shape law (from p); 1: Table 1 material (from W)
-    const WallDev *W;
     double Lv, cw;
     __device__ __forceinline__ double operator()(int la, int k) const
     {
@@ -73,11 +71,17 @@ __device__ __forceinline__ ImpK imp_law_k(const ImpLaw &m, int la, double phi)
     k.kX = m(la, L_BTM) * k.kM;
     return k;
 }
+// LAW: 0 = the shape law, 1 = the Table 1 material (the layer scales of the
+// wall times that material's functions, evaluated once per face)
+template <int LAW>
 __device__ __forceinline__ ImpK imp_face(const ImpLaw &m, int la, int lb, double T, double P)
 {
-    if (m.law == 1) {          // Table 1 material (layer scales from the descriptor)
-        const KCoef<double> k = t1_face_k<double>(*m.W, la, lb, T - 273.15, P, m.Lv);
-        return {k.kT, k.kM, k.kX};
+    if constexpr (LAW == 1) {
+        const KCoef<double> f = t1_kfun<double>(T - 273.15, P, m.Lv);
+        const ImpK a = {f.kT * m(la, L_K0), f.kM * m(la, L_KM0), f.kX * m(la, L_KM0)};
+        if (la == lb) return a;
+        const ImpK b = {f.kT * m(lb, L_K0), f.kM * m(lb, L_KM0), f.kX * m(lb, L_KM0)};
+        return {harm(a.kT, b.kT), harm(a.kM, b.kM), harm(a.kX, b.kX)};
     }
     const double phi = P / psat_th(T - 273.15);
     const ImpK a = imp_law_k(m, la, phi);
@@ -85,11 +89,15 @@ __device__ __forceinline__ ImpK imp_face(const ImpLaw &m, int la, int lb, double
     const ImpK b = imp_law_k(m, lb, phi);
     return {harm(a.kT, b.kT), harm(a.kM, b.kM), harm(a.kX, b.kX)};
 }
+template <int LAW>
 __device__ __forceinline__ ImpC imp_node(const ImpLaw &m, int la, double T, double P)
 {
     const double th = T - 273.15;
-    if (m.law == 1) {
-        const CCoef<double> c = t1_law_c<double>(m.W->lay[la], th, P, m.cw);
+    if constexpr (LAW == 1) {
+        double ml[L_COUNT];
+        ml[L_C0] = m(la, L_C0);
+        ml[L_CM0] = m(la, L_CM0);
+        const CCoef<double> c = t1_law_c<double>(ml, th, P, m.cw);
         return {c.cT, c.cM, c.cX};
     }
     const double phi = P / psat_th(th);
@@ -116,12 +124,21 @@ __device__ __forceinline__ ImpC imp_node(const ImpLaw &m, int la, double T, doub
 // 65,536-wall batches: the sweeps' dependent FP64 chains then had nothing to
 // hide their latency behind.)
 //
+// Each sweep keeps the next kPf nodes' data in a register ring: step s reads
+// slot s % kPf and refills it with the node of step s + kPf (the index
+// clamped to the half, so that every read is issued).  The loop runs in
+// blocks of kPf steps with the slot a compile-time index and no branch, so
+// the wait for a node's data covers only the reads issued kPf steps before;
+// the surface node (step 0) is peeled off and the last partial block is
+// guarded.
+//
 // One time step n -> n+1 of every wall; iters[w] accumulates the number of
 // sub-iterations.
+template <int LAW>
 __global__ void __launch_bounds__(kImpLanes) __attribute__((amdgpu_waves_per_eu(2)))
 k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ groups, ImpArrays A,
            int64_t n, double dt, double theta, double eta, int max_it, double Lv,
-           int law_id, double cw, int64_t *__restrict__ iters)
+           double cw, int64_t *__restrict__ iters)
 {
     __shared__ double s_law[kMaxLayers * L_COUNT][kImpLanes];
     const ImpGroup G = groups[blockIdx.x];
@@ -133,7 +150,7 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
     const WallDev &W = walls[w];
     const int nx = W.nx;
     for (int q = 0; q < kMaxLayers * L_COUNT; ++q) s_law[q][lane] = W.lay[q / L_COUNT][q % L_COUNT];
-    const ImpLaw law{&s_law[0][lane], law_id, &W, Lv, cw};
+    const ImpLaw law{&s_law[0][lane], Lv, cw};
     // first node of layers 1 and 2 (node j is in the first layer whose right
     // end is >= x_j), so that a node's layer is two compares
     int jb1 = nx, jb2 = nx;
@@ -172,11 +189,11 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
     const int j0 = up ? nx - 1 : 0;
     const int ns = up ? nx - 1 - m : m;
     const int side = up ? 1 : 0;
-    auto fwd = [&](int s) { return j0 + d * s; };        // node of forward step s (s = ns: m)
-    auto bwd = [&](int s) { return m - d * (1 + s); };   // node of back step s
+    auto fwd = [&](int s) { return j0 + d * min(s, ns); };          // node of forward step s (ns: m)
+    auto bwd = [&](int s) { return m - d * (1 + min(s, ns - 1)); }; // node of back step s
 
     // outdoor air and surface heat sources (constant + incident radiation)
-    // of this lane's surface at t^n and t^{n+1}
+    // of this lane's surface at t^n and t^{n+1}, and its exchange coefficients
     const double t0 = (double)n * dt, t1 = (double)(n + 1) * dt;
     const double Ti0 = sine_at(W.Tamb[side], t0);
     const double Pi0 = sine_at(W.RHamb[side], t0) * psat_th(Ti0 - 273.15);
@@ -184,81 +201,82 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
     const double Pi1 = sine_at(W.RHamb[side], t1) * psat_th(Ti1 - 273.15);
     const double Q0 = W.qinf[side] + incident(W, side, t0);
     const double Q1 = W.qinf[side] + incident(W, side, t1);
+    const double hM = W.hM[side], gI = W.ginf[side], hT = W.hT[side], hL = Lv * W.hM[side];
 
-    // Each sweep keeps the data of the next kPf nodes in a register ring:
-    // the loads of node (step + kPf) are issued while a node is computed, so
-    // HBM latency overlaps the coefficient arithmetic.  (Ring slots are
-    // indexed by the unrolled inner loop, so the ring stays in registers.)
-    // Two nodes ahead and two waves per SIMD: on the 65,536-wall batches
-    // that measured 10-12 % faster than eight ahead at one wave per SIMD
-    // (one lane per wall), and the twisted sweeps at eight ahead needed
-    // more registers than two waves leave.
-    constexpr int kPf = 2;
+    // (three slots: 15.0 ms per step on the 65,536 x 1001 batch against 19.5
+    // with a shifting queue, whose register moves waited for reads in flight)
+    constexpr int kPf = 3;
     int it = 0;
     for (;;) {
         ++it;
         // the iterate: level n on the first pass, the last solution after
         const double *Tk = it == 1 ? To : Tw;
         const double *Pk = it == 1 ? Po : Pw;
-        // ---- moisture: forward elimination with coefficients on the fly
         double xm;                                       // the meeting node's new value
+        // ---- moisture: forward elimination with coefficients on the fly
         {
-            double rTk[kPf], rTo[kPf], rPk[kPf], rPo[kPf];   // node of step s + 1
+            double qTk[kPf], qTo[kPf], qPk[kPf], qPo[kPf];   // nodes of steps s + 1 .. s + kPf
 #pragma unroll
             for (int q = 0; q < kPf; ++q) {
-                if (1 + q <= ns) {
-                    const int jj = fwd(1 + q);
-                    rTk[q] = Tk[at(jj)]; rTo[q] = To[at(jj)]; rPk[q] = Pk[at(jj)]; rPo[q] = Po[at(jj)];
-                }
+                const int jj = fwd(1 + q);
+                qTk[q] = Tk[at(jj)]; qTo[q] = To[at(jj)]; qPk[q] = Pk[at(jj)]; qPo[q] = Po[at(jj)];
             }
             int la = layer_of(j0);
             double Tsj = theta * Tk[at(j0)] + th1 * To[at(j0)];
             double Psj = theta * Pk[at(j0)] + th1 * Po[at(j0)];
             double Poj = Po[at(j0)], Pol = 0.0;
             double gl = 0.0, rl = 0.0, el = 0.0;         // near face kM / dx; previous r, e
-            for (int s0 = 0; s0 < ns; s0 += kPf) {
+            // step s reads its far node from slot s % kPf and refills the slot
+            // with the far node of step s + kPf
+            auto step = [&](const bool surf, int s, double &fTk, double &fTo, double &fPk, double &fPo) {
+                const int j = fwd(s);
+                const ImpC cn = imp_node<LAW>(law, la, Tsj, Psj);
+                const int lb = layer_of(j + d);
+                const double Tsr = theta * fTk + th1 * fTo;
+                const double Psr = theta * fPk + th1 * fPo;
+                const double Por = fPo;
+                const double gr = imp_face<LAW>(law, la, lb, 0.5 * (Tsj + Tsr), 0.5 * (Psj + Psr)).kM / dx;
+                {
+                    const int jn = fwd(s + 1 + kPf);
+                    fTk = Tk[at(jn)]; fTo = To[at(jn)]; fPk = Pk[at(jn)]; fPo = Po[at(jn)];
+                }
+                const double width = surf ? 0.5 * dx : dx;
+                double diag = width * cn.cM / dt, rhs = diag * Poj, a = 0.0;
+                if (!surf) { diag += theta * gl; a = -theta * gl; rhs += th1 * gl * (Pol - Poj); }
+                diag += theta * gr;
+                const double c = -theta * gr;
+                rhs += th1 * gr * (Por - Poj);
+                if (surf) {
+                    diag += theta * hM;
+                    rhs += theta * (hM * Pi1 + gI) + th1 * (hM * (Pi0 - Poj) + gI);
+                }
+                const double den = diag - a * rl;
+                rl = c / den;
+                el = (rhs - a * el) / den;
+                cp[at(j)] = rl;
+                dp[at(j)] = el;
+                gl = gr; Pol = Poj; Poj = Por; Tsj = Tsr; Psj = Psr; la = lb;
+            };
+            step(true, 0, qTk[0], qTo[0], qPk[0], qPo[0]);
+            int s = 1;
+            for (; s + kPf <= ns; s += kPf) {
 #pragma unroll
                 for (int q = 0; q < kPf; ++q) {
-                    const int s = s0 + q;
-                    if (s < ns) {
-                        const int j = fwd(s);
-                        const ImpC cn = imp_node(law, la, Tsj, Psj);
-                        const int lb = layer_of(j + d);
-                        const double Tsr = theta * rTk[q] + th1 * rTo[q];
-                        const double Psr = theta * rPk[q] + th1 * rPo[q];
-                        const double Por = rPo[q];
-                        const double gr = imp_face(law, la, lb, 0.5 * (Tsj + Tsr), 0.5 * (Psj + Psr)).kM / dx;
-                        if (s + 1 + kPf <= ns) {
-                            const int jn = fwd(s + 1 + kPf);
-                            rTk[q] = Tk[at(jn)]; rTo[q] = To[at(jn)]; rPk[q] = Pk[at(jn)]; rPo[q] = Po[at(jn)];
-                        }
-                        const bool surf = s == 0;
-                        const double width = surf ? 0.5 * dx : dx;
-                        double diag = width * cn.cM / dt, rhs = diag * Poj, a = 0.0;
-                        if (!surf) { diag += theta * gl; a = -theta * gl; rhs += th1 * gl * (Pol - Poj); }
-                        diag += theta * gr;
-                        const double c = -theta * gr;
-                        rhs += th1 * gr * (Por - Poj);
-                        if (surf) {
-                            const double h = W.hM[side];
-                            diag += theta * h;
-                            rhs += theta * (h * Pi1 + W.ginf[side]) + th1 * (h * (Pi0 - Poj) + W.ginf[side]);
-                        }
-                        const double den = diag - a * rl;
-                        rl = c / den;
-                        el = (rhs - a * el) / den;
-                        cp[at(j)] = rl;
-                        dp[at(j)] = el;
-                        gl = gr; Pol = Poj; Poj = Por; Tsj = Tsr; Psj = Psr; la = lb;
-                    }
+                    const int k = (1 + q) % kPf;
+                    step(false, s + q, qTk[k], qTo[k], qPk[k], qPo[k]);
                 }
+            }
+#pragma unroll
+            for (int q = 0; q + 1 < kPf; ++q) {
+                const int k = (1 + q) % kPf;
+                if (s + q < ns) step(false, s + q, qTk[k], qTo[k], qPk[k], qPo[k]);
             }
             // the meeting node: A takes B's far face, its neighbour's level n
             // and B's last r, e (each lane's carried state is now node m)
             const double gB = __shfl_xor(gl, kImpWalls), PoB = __shfl_xor(Pol, kImpWalls);
             const double rB = __shfl_xor(rl, kImpWalls), eB = __shfl_xor(el, kImpWalls);
             {
-                const ImpC cn = imp_node(law, la, Tsj, Psj);
+                const ImpC cn = imp_node<LAW>(law, la, Tsj, Psj);
                 const double diag0 = dx * cn.cM / dt;
                 const double diag = diag0 + theta * (gl + gB);
                 const double rhs = diag0 * Poj + th1 * gl * (Pol - Poj) + th1 * gB * (PoB - Poj);
@@ -276,41 +294,43 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
                 dP = fabs(xm - Pk[at(m)]);
                 sP = fabs(xm);
             }
-            double rc[kPf], rd[kPf], rk[kPf];                 // node of back step s
+            double qc[kPf], qd[kPf], qk[kPf];                 // nodes of back steps s .. s + kPf - 1
 #pragma unroll
             for (int q = 0; q < kPf; ++q) {
-                if (q < ns) { const int jj = bwd(q); rc[q] = cp[at(jj)]; rd[q] = dp[at(jj)]; rk[q] = Pk[at(jj)]; }
+                const int jj = bwd(q);
+                qc[q] = cp[at(jj)]; qd[q] = dp[at(jj)]; qk[q] = Pk[at(jj)];
             }
             double x = xm;
-            for (int s0 = 0; s0 < ns; s0 += kPf) {
-#pragma unroll
-                for (int q = 0; q < kPf; ++q) {
-                    const int s = s0 + q;
-                    if (s < ns) {
-                        x = rd[q] - rc[q] * x;
-                        Pn[at(bwd(s))] = x;
-                        dP = fmax(dP, fabs(x - rk[q]));
-                        sP = fmax(sP, fabs(x));
-                        if (s + kPf < ns) {
-                            const int jn = bwd(s + kPf);
-                            rc[q] = cp[at(jn)]; rd[q] = dp[at(jn)]; rk[q] = Pk[at(jn)];
-                        }
-                    }
+            auto bstep = [&](int s, double &fc, double &fd, double &fk) {
+                x = fd - fc * x;
+                const double pk = fk;
+                {
+                    const int jn = bwd(s + kPf);
+                    fc = cp[at(jn)]; fd = dp[at(jn)]; fk = Pk[at(jn)];
                 }
+                Pn[at(bwd(s))] = x;
+                dP = fmax(dP, fabs(x - pk));
+                sP = fmax(sP, fabs(x));
+            };
+            int s = 0;
+            for (; s + kPf <= ns; s += kPf) {
+#pragma unroll
+                for (int q = 0; q < kPf; ++q) bstep(s + q, qc[q], qd[q], qk[q]);
             }
+#pragma unroll
+            for (int q = 0; q + 1 < kPf; ++q)
+                if (s + q < ns) bstep(s + q, qc[q], qd[q], qk[q]);
         }
         // the other lane reads the new moisture next to the meeting node
         __threadfence_block();
         // ---- heat with the new vapour pressure
         {
-            double rTk[kPf], rTo[kPf], rPk[kPf], rPo[kPf], rPn[kPf];   // node of step s + 1
+            double qTk[kPf], qTo[kPf], qPk[kPf], qPo[kPf], qPn[kPf];   // nodes of steps s + 1 ..
 #pragma unroll
             for (int q = 0; q < kPf; ++q) {
-                if (1 + q <= ns) {
-                    const int jj = fwd(1 + q);
-                    rTk[q] = Tk[at(jj)]; rTo[q] = To[at(jj)]; rPk[q] = Pk[at(jj)]; rPo[q] = Po[at(jj)];
-                    rPn[q] = Pn[at(jj)];
-                }
+                const int jj = fwd(1 + q);
+                qTk[q] = Tk[at(jj)]; qTo[q] = To[at(jj)]; qPk[q] = Pk[at(jj)]; qPo[q] = Po[at(jj)];
+                qPn[q] = Pn[at(jj)];
             }
             int la = layer_of(j0);
             double Tsj = theta * Tk[at(j0)] + th1 * To[at(j0)];
@@ -318,58 +338,65 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
             double Toj = To[at(j0)], Poj = Po[at(j0)], Pnj = Pn[at(j0)];
             double Tol = 0.0, Pol = 0.0, Pnl = 0.0;
             double gTl = 0.0, gXl = 0.0, rl = 0.0, el = 0.0;
-            for (int s0 = 0; s0 < ns; s0 += kPf) {
+            auto step = [&](const bool surf, int s, double &fTk, double &fTo, double &fPk, double &fPo,
+                            double &fPn) {
+                const int j = fwd(s);
+                const ImpC cn = imp_node<LAW>(law, la, Tsj, Psj);
+                const int lb = layer_of(j + d);
+                const double Tsr = theta * fTk + th1 * fTo;
+                const double Psr = theta * fPk + th1 * fPo;
+                const double Tor = fTo, Por = fPo, Pnr = fPn;
+                const ImpK kf = imp_face<LAW>(law, la, lb, 0.5 * (Tsj + Tsr), 0.5 * (Psj + Psr));
+                const double gTr = kf.kT / dx, gXr = kf.kX / dx;
+                {
+                    const int jn = fwd(s + 1 + kPf);
+                    fTk = Tk[at(jn)]; fTo = To[at(jn)]; fPk = Pk[at(jn)]; fPo = Po[at(jn)];
+                    fPn = Pn[at(jn)];
+                }
+                const double width = surf ? 0.5 * dx : dx;
+                double diag = width * cn.cT / dt;
+                double rhs = diag * Toj - width * cn.cX * (Pnj - Poj) / dt;
+                double a = 0.0;
+                if (!surf) {
+                    diag += theta * gTl; a = -theta * gTl;
+                    rhs += th1 * gTl * (Tol - Toj) + gXl * (theta * (Pnl - Pnj) + th1 * (Pol - Poj));
+                }
+                diag += theta * gTr;
+                const double c = -theta * gTr;
+                rhs += th1 * gTr * (Tor - Toj) + gXr * (theta * (Pnr - Pnj) + th1 * (Por - Poj));
+                if (surf) {
+                    diag += theta * hT;
+                    rhs += theta * (hT * Ti1 + hL * (Pi1 - Pnj) + Q1)
+                         + th1 * (hT * (Ti0 - Toj) + hL * (Pi0 - Poj) + Q0);
+                }
+                const double den = diag - a * rl;
+                rl = c / den;
+                el = (rhs - a * el) / den;
+                cp[at(j)] = rl;
+                dp[at(j)] = el;
+                gTl = gTr; gXl = gXr; Tol = Toj; Pol = Poj; Pnl = Pnj;
+                Toj = Tor; Poj = Por; Pnj = Pnr; Tsj = Tsr; Psj = Psr; la = lb;
+            };
+            step(true, 0, qTk[0], qTo[0], qPk[0], qPo[0], qPn[0]);
+            int s = 1;
+            for (; s + kPf <= ns; s += kPf) {
 #pragma unroll
                 for (int q = 0; q < kPf; ++q) {
-                    const int s = s0 + q;
-                    if (s < ns) {
-                        const int j = fwd(s);
-                        const ImpC cn = imp_node(law, la, Tsj, Psj);
-                        const int lb = layer_of(j + d);
-                        const double Tsr = theta * rTk[q] + th1 * rTo[q];
-                        const double Psr = theta * rPk[q] + th1 * rPo[q];
-                        const double Tor = rTo[q], Por = rPo[q], Pnr = rPn[q];
-                        const ImpK kf = imp_face(law, la, lb, 0.5 * (Tsj + Tsr), 0.5 * (Psj + Psr));
-                        const double gTr = kf.kT / dx, gXr = kf.kX / dx;
-                        if (s + 1 + kPf <= ns) {
-                            const int jn = fwd(s + 1 + kPf);
-                            rTk[q] = Tk[at(jn)]; rTo[q] = To[at(jn)]; rPk[q] = Pk[at(jn)]; rPo[q] = Po[at(jn)];
-                            rPn[q] = Pn[at(jn)];
-                        }
-                        const bool surf = s == 0;
-                        const double width = surf ? 0.5 * dx : dx;
-                        double diag = width * cn.cT / dt;
-                        double rhs = diag * Toj - width * cn.cX * (Pnj - Poj) / dt;
-                        double a = 0.0;
-                        if (!surf) {
-                            diag += theta * gTl; a = -theta * gTl;
-                            rhs += th1 * gTl * (Tol - Toj) + gXl * (theta * (Pnl - Pnj) + th1 * (Pol - Poj));
-                        }
-                        diag += theta * gTr;
-                        const double c = -theta * gTr;
-                        rhs += th1 * gTr * (Tor - Toj) + gXr * (theta * (Pnr - Pnj) + th1 * (Por - Poj));
-                        if (surf) {
-                            const double hT = W.hT[side], hL = Lv * W.hM[side];
-                            diag += theta * hT;
-                            rhs += theta * (hT * Ti1 + hL * (Pi1 - Pnj) + Q1)
-                                 + th1 * (hT * (Ti0 - Toj) + hL * (Pi0 - Poj) + Q0);
-                        }
-                        const double den = diag - a * rl;
-                        rl = c / den;
-                        el = (rhs - a * el) / den;
-                        cp[at(j)] = rl;
-                        dp[at(j)] = el;
-                        gTl = gTr; gXl = gXr; Tol = Toj; Pol = Poj; Pnl = Pnj;
-                        Toj = Tor; Poj = Por; Pnj = Pnr; Tsj = Tsr; Psj = Psr; la = lb;
-                    }
+                    const int k = (1 + q) % kPf;
+                    step(false, s + q, qTk[k], qTo[k], qPk[k], qPo[k], qPn[k]);
                 }
+            }
+#pragma unroll
+            for (int q = 0; q + 1 < kPf; ++q) {
+                const int k = (1 + q) % kPf;
+                if (s + q < ns) step(false, s + q, qTk[k], qTo[k], qPk[k], qPo[k], qPn[k]);
             }
             const double gTB = __shfl_xor(gTl, kImpWalls), gXB = __shfl_xor(gXl, kImpWalls);
             const double ToB = __shfl_xor(Tol, kImpWalls), PoB = __shfl_xor(Pol, kImpWalls);
             const double PnB = __shfl_xor(Pnl, kImpWalls);
             const double rB = __shfl_xor(rl, kImpWalls), eB = __shfl_xor(el, kImpWalls);
             {
-                const ImpC cn = imp_node(law, la, Tsj, Psj);
+                const ImpC cn = imp_node<LAW>(law, la, Tsj, Psj);
                 const double diag0 = dx * cn.cT / dt;
                 const double diag = diag0 + theta * (gTl + gTB);
                 const double rhs = diag0 * Toj - dx * cn.cX * (Pnj - Poj) / dt
@@ -391,36 +418,36 @@ k_imp_step(const WallDev *__restrict__ walls, const ImpGroup *__restrict__ group
                 Tw[at(m)] = xm;
                 Pw[at(m)] = pn;
             }
-            double rc[kPf], rd[kPf], rk[kPf], rn[kPf];        // node of back step s
+            double qc[kPf], qd[kPf], qk[kPf], qn[kPf];        // nodes of back steps s ..
 #pragma unroll
             for (int q = 0; q < kPf; ++q) {
-                if (q < ns) {
-                    const int jj = bwd(q);
-                    rc[q] = cp[at(jj)]; rd[q] = dp[at(jj)]; rk[q] = Tk[at(jj)]; rn[q] = Pn[at(jj)];
-                }
+                const int jj = bwd(q);
+                qc[q] = cp[at(jj)]; qd[q] = dp[at(jj)]; qk[q] = Tk[at(jj)]; qn[q] = Pn[at(jj)];
             }
             double x = xm;
-            for (int s0 = 0; s0 < ns; s0 += kPf) {
-#pragma unroll
-                for (int q = 0; q < kPf; ++q) {
-                    const int s = s0 + q;
-                    if (s < ns) {
-                        x = rd[q] - rc[q] * x;
-                        dT = fmax(dT, fabs(x - rk[q]));
-                        sT = fmax(sT, fabs(x));
-                        const double pn = rn[q];
-                        // node jn is not written before it is read here: the
-                        // ring reads it now, the write of node jn comes later
-                        if (s + kPf < ns) {
-                            const int jn = bwd(s + kPf);
-                            rc[q] = cp[at(jn)]; rd[q] = dp[at(jn)]; rk[q] = Tk[at(jn)]; rn[q] = Pn[at(jn)];
-                        }
-                        const int j = bwd(s);
-                        Tw[at(j)] = x;
-                        Pw[at(j)] = pn;
-                    }
+            // node s + kPf is read before this step's write of node s (a node
+            // is written only at its own step, after every read of it)
+            auto bstep = [&](int s, double &fc, double &fd, double &fk, double &fn) {
+                x = fd - fc * x;
+                const double tk = fk, pn = fn;
+                {
+                    const int jn = bwd(s + kPf);
+                    fc = cp[at(jn)]; fd = dp[at(jn)]; fk = Tk[at(jn)]; fn = Pn[at(jn)];
                 }
+                const int j = bwd(s);
+                dT = fmax(dT, fabs(x - tk));
+                sT = fmax(sT, fabs(x));
+                Tw[at(j)] = x;
+                Pw[at(j)] = pn;
+            };
+            int s = 0;
+            for (; s + kPf <= ns; s += kPf) {
+#pragma unroll
+                for (int q = 0; q < kPf; ++q) bstep(s + q, qc[q], qd[q], qk[q], qn[q]);
             }
+#pragma unroll
+            for (int q = 0; q + 1 < kPf; ++q)
+                if (s + q < ns) bstep(s + q, qc[q], qd[q], qk[q], qn[q]);
         }
         // the next sub-iteration's sweeps read the other lane's new nodes
         __threadfence_block();

@@ -1305,10 +1305,10 @@ dfhm_status dfhm_implicit_step_n(dfhm_implicit *ic, int64_t n_steps)
 {
     if (!ic || n_steps < 0) return DFHM_E_INVAL;
     for (int64_t k = 0; k < n_steps; ++k) {
-        hipLaunchKernelGGL(k_imp_step, dim3(ic->ngroups), dim3(kImpLanes), 0, ic->stream, ic->d_walls,
+        auto kern = ic->cfg.law == DFHM_LAW_TABLE1 ? k_imp_step<1> : k_imp_step<0>;
+        hipLaunchKernelGGL(kern, dim3(ic->ngroups), dim3(kImpLanes), 0, ic->stream, ic->d_walls,
                            ic->d_groups, ic->A, ic->n, ic->cfg.dt_s, ic->cfg.theta, ic->cfg.eta,
-                           (int)ic->cfg.max_iters, ic->cfg.Lv, (int)ic->cfg.law, ic->cfg.cw,
-                           ic->d_iters);
+                           (int)ic->cfg.max_iters, ic->cfg.Lv, ic->cfg.cw, ic->d_iters);
         ic->n += 1;
     }
     if (hipGetLastError() != hipSuccess) { ic->err = "kernel launch failed"; return DFHM_E_DEVICE; }
