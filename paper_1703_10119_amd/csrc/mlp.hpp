@@ -7,6 +7,7 @@
 // matrices are row-major; BF16 values are stored as uint16 (round to nearest
 // even from FP32).
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -283,6 +284,7 @@ __global__ void k_pack_swizzled(const float *__restrict__ w, uint16_t *__restric
 // accumulation over K in steps of 32 in ascending order, GELU, BF16
 // rounding -- so the two paths agree bit for bit.
 constexpr int FI_M = 128, FI_NW = 8, FI_PAD = 8, FI_KC = 64;
+constexpr int FI_PF = 2;   // weight ring depth (K steps read ahead); divides 4 = K steps per 128 of width
 
 // Layer operands by base and stride (no per-layer pointer table, which the
 // kernel would have to copy to scratch memory to index), weights in
@@ -412,24 +414,33 @@ k_mlp_infer_fused(FusedNet net, const uint16_t *__restrict__ x, int ldx, int64_t
     for (int l = 1; l < net.depth; ++l) {
         const uint16_t *__restrict__ Wl = net.Wh + (l - 1) * net.wh_stride;
         init(net.bh + (l - 1) * net.bh_stride);
-        bf16x8 wf[NJ], wn[NJ];
+        // the weights of K steps ks .. ks + FI_PF - 1 in a ring of FI_PF
+        // slots: step ks reads slot ks % FI_PF (a compile-time index in the
+        // unrolled block) and refills it with step ks + FI_PF (clamped), so
+        // the wait for a fragment covers only reads issued FI_PF steps before
+        bf16x8 wr[FI_PF][NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) wf[j] = wfrag(Wl, KSW, j, 0);
-#pragma unroll 2
-        for (int ks = 0; ks < KSW; ++ks) {
-            if (ks + 1 < KSW) {
+        for (int p = 0; p < FI_PF; ++p)
 #pragma unroll
-                for (int j = 0; j < NJ; ++j) wn[j] = wfrag(Wl, KSW, j, ks + 1);
+            for (int j = 0; j < NJ; ++j) wr[p][j] = wfrag(Wl, KSW, j, p);
+        for (int ks0 = 0; ks0 < KSW; ks0 += FI_PF) {
+#pragma unroll
+            for (int p = 0; p < FI_PF; ++p) {
+                const int ks = ks0 + p;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const bf16x8 af = *(const bf16x8 *)(lds_act + (i * 16 + fr) * LDA + ks * 32 + fk);
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[p][j], af, acc[i][j], 0, 0, 0);
+                }
+                const int kn = min(ks + FI_PF, KSW - 1);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) wr[p][j] = wfrag(Wl, KSW, j, kn);
+                // keep the next step's LDS reads below this step's MFMAs (hoisted,
+                // they took the registers of a deeper schedule and spilled)
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const bf16x8 af = *(const bf16x8 *)(lds_act + (i * 16 + fr) * LDA + ks * 32 + fk);
-#pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af, acc[i][j], 0, 0, 0);
-            }
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) wf[j] = wn[j];
         }
         __syncthreads();          // every wave has read the layer's input
         hidden_out();
@@ -444,16 +455,32 @@ k_mlp_infer_fused(FusedNet net, const uint16_t *__restrict__ x, int ldx, int64_t
             const float4 bb = j < no ? *(const float4 *)(net.bo + j * 16 + nl) : make_float4(0.f, 0.f, 0.f, 0.f);
             o[j] = (f32x4){bb.x, bb.y, bb.z, bb.w};
         }
-        for (int ks = 0; ks < KSW; ++ks) {
-            const bf16x8 af = *(const bf16x8 *)(lds_act + (wave * 16 + fr) * LDA + ks * 32 + fk);
+        // the same weight ring as the hidden layers, for one or two tiles
+        auto out_tiles = [&](auto no_c) {
+            constexpr int NO = decltype(no_c)::value;
+            auto ofrag = [&](int j, int ks) {
+                return __builtin_bit_cast(bf16x8, *(const uint4 *)(net.Wo + (((size_t)j * KSW + ks) * 64 + lane) * 8));
+            };
+            bf16x8 wr[FI_PF][NO];
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                if (j < no) {
-                    const bf16x8 wf = __builtin_bit_cast(
-                        bf16x8, *(const uint4 *)(net.Wo + (((size_t)j * KSW + ks) * 64 + lane) * 8));
-                    o[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf, af, o[j], 0, 0, 0);
+            for (int p = 0; p < FI_PF; ++p)
+#pragma unroll
+                for (int j = 0; j < NO; ++j) wr[p][j] = ofrag(j, p);
+            for (int ks0 = 0; ks0 < KSW; ks0 += FI_PF) {
+#pragma unroll
+                for (int p = 0; p < FI_PF; ++p) {
+                    const int ks = ks0 + p;
+                    const bf16x8 af = *(const bf16x8 *)(lds_act + (wave * 16 + fr) * LDA + ks * 32 + fk);
+#pragma unroll
+                    for (int j = 0; j < NO; ++j) o[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[p][j], af, o[j], 0, 0, 0);
+                    const int kn = min(ks + FI_PF, KSW - 1);
+#pragma unroll
+                    for (int j = 0; j < NO; ++j) wr[p][j] = ofrag(j, kn);
                 }
-        }
+            }
+        };
+        if (no == 2) out_tiles(std::integral_constant<int, 2>{});
+        else out_tiles(std::integral_constant<int, 1>{});
         const int64_t row = m0 + wave * 16 + fr;
         if (row < batch) {
 #pragma unroll
