@@ -500,17 +500,39 @@ __global__ void k_sum_partials(const float *__restrict__ part, int nsplit, int64
     out[i] = s;
 }
 
-// Column sums of a BF16 matrix [rows][cols] into FP32 partials
-// part[blockIdx.y][col] over row range blockIdx.y * rchunk ...
-__global__ void k_colsum_bf16(const uint16_t *__restrict__ x, int rows, int cols, int rchunk,
-                              float *__restrict__ part)
+// Column sums of a BF16 matrix [rows][cols] (cols a multiple of 8) into FP32
+// partials part[blockIdx.y][col] over the row range [blockIdx.y * rchunk,
+// + rchunk): 256 lanes, lane (g, c) sums columns 8 c .. 8 c + 7 of block
+// column group blockIdx.x over the rows g, g + 4, ... of the range with one
+// 16-byte read per row, and the four row groups meet in LDS.
+__global__ void __launch_bounds__(256) k_colsum_bf16(const uint16_t *__restrict__ x, int rows, int cols,
+                                                     int rchunk, float *__restrict__ part)
 {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= cols) return;
+    __shared__ float red[4][64][9];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int col0 = (blockIdx.x * 64 + c) * 8;
     const int r0 = blockIdx.y * rchunk, r1 = min(rows, r0 + rchunk);
-    float s = 0.f;
-    for (int r = r0; r < r1; ++r) s += bf2f(x[(int64_t)r * cols + col]);
-    part[(int64_t)blockIdx.y * cols + col] = s;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (col0 < cols) {
+        for (int r = r0 + g; r < r1; r += 4) {
+            const uint4 v = *(const uint4 *)(x + (int64_t)r * cols + col0);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                s[2 * h] += __uint_as_float(w[h] << 16);
+                s[2 * h + 1] += __uint_as_float(w[h] & 0xffff0000u);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[g][c][e] = s[e];
+    __syncthreads();
+    if (g == 0 && col0 < cols) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            part[(int64_t)blockIdx.y * cols + col0 + e] =
+                (red[0][c][e] + red[1][c][e]) + (red[2][c][e] + red[3][c][e]);
+    }
 }
 
 // Loss of a head with F = n_out / 2 targets: outputs z[b][0..F) are the

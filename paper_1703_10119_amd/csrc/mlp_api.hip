@@ -17,6 +17,9 @@
 
 using namespace dfhm;
 
+// rows per partial of the bias-gradient column sums
+constexpr int kColsumRows = 256;
+
 namespace {
 constexpr int kOutPad = 32;   // output layer rows padded for the GEMM tiles
 
@@ -222,10 +225,10 @@ void backward(dfhm_mlp *m, int batch)
         hipLaunchKernelGGL(k_sum_partials, dim3(blocks_of(nw, 256)), dim3(256), 0, m->stream,
                            m->part, nsplit, nw, m->g + ly.w_off);
         // bias gradient: column sums of dz
-        const int rchunk = 256;
+        const int rchunk = kColsumRows;
         const int nrc = (batch + rchunk - 1) / rchunk;
         float *cs = m->part + (size_t)nsplit * nw;
-        hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks_of(Nl, 64), nrc), dim3(64), 0, m->stream, dz,
+        hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks_of(Nl, 512), nrc), dim3(256), 0, m->stream, dz,
                            batch, Nl, rchunk, cs);
         hipLaunchKernelGGL(k_sum_partials, dim3(blocks_of(Nl, 256)), dim3(256), 0, m->stream, cs,
                            nrc, (int64_t)Nl, m->g + ly.b_off);
@@ -365,7 +368,7 @@ dfhm_status dfhm_mlp_create(const dfhm_mlp_config *cfg, dfhm_mlp **out)
         maxw = std::max(maxw, (size_t)Nl * ly.K);
     }
     const size_t maxn = (size_t)std::max(cfg->width, kOutPad);
-    m->part_n = 16 * maxw + (size_t)((B + 255) / 256) * maxn + 1024;
+    m->part_n = 16 * maxw + (size_t)((B + kColsumRows - 1) / kColsumRows) * maxn + 1024;
     if (dalloc(m, &m->part, m->part_n)) return bail(DFHM_E_NOMEM);
     // He-style initialisation from the seed; biases zero; padding rows zero
     std::mt19937_64 rng(cfg->seed);
